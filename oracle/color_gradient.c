@@ -1,0 +1,287 @@
+/*
+ * Oracle: two-component colour-gradient lattice Boltzmann, without and with
+ * populations (test infrastructure only; see oracle.h).
+ *
+ * The paper carries two species on one flow field with the colour-gradient
+ * model (Sec. III.A): per species only a density is stored (2 extra arrays),
+ * the density gradient is evaluated on the post-streaming state before the
+ * collision, and "perturbation" and "re-colouring" operators are applied to
+ * the populations of Eq. 8.  The paper names the model but does not print
+ * its operators; the readings used here are:
+ *
+ *   phase field     phi = (rho1 - rho2)/(rho1 + rho2)           (Sec. III.B)
+ *   colour gradient G = (1/c_s^2) sum_i w_i c_i phi(y + c_i)   (isotropic)
+ *   normal          n = G/|G| if |G| > EPS_G, else n = 0 and both operators
+ *                   below vanish
+ *   perturbation    Df_i = (A/2)|G| [w_i (c_i.n)^2 - B_i], B_0 = w_0 - 2/3,
+ *                   B_i = w_i otherwise (three-dimensional operator of Liu,
+ *                   Valocchi and Kang); it carries no mass and no momentum,
+ *                   and its second moment is
+ *                   DP_ab = (A/9)|G| (n_a n_b - delta_ab);
+ *                   surface tension sigma = 2 A tau / 9
+ *   recolouring     f^k_i = (rho^k/rho) f'_i
+ *                           + s_k beta (rho1 rho2/rho) w_i (c_i.n)/|c_i|,
+ *                   s_1 = +1, s_2 = -1, zero for the rest velocity
+ *                   (Latva-Kokko and Rothman form with f^eq(rho, u=0) = w_i rho)
+ *   one relaxation time for the mixture (viscosity ratio one, Sec. IV)
+ *
+ * Without populations the perturbation enters through its second moment
+ * only: the collided tensor is P' = P^eq + (1-omega)(P - P^eq) + DP and the
+ * populations are the Eq. 4 reconstruction of it, so the operator's
+ * fourth-order part is a ghost and is dropped with the others.  The stored
+ * state is the post-streaming one, so the gradient is available before the
+ * collision, as the paper requires.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle.h"
+
+#define EPS_G 1e-8
+
+/* Two-component SoA layout: rho1, rho2, jx, jy, jz, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz. */
+static void load_node2(const double *H, long N, long n, double *rho1, double *rho2, double j[3],
+                       double P[3][3])
+{
+    double p6[6];
+    *rho1 = H[0 * N + n];
+    *rho2 = H[1 * N + n];
+    for (int a = 0; a < 3; ++a) j[a] = H[(2 + a) * N + n];
+    for (int k = 0; k < 6; ++k) p6[k] = H[(5 + k) * N + n];
+    ora_unpack_tensor(p6, P);
+}
+
+static void store_node2(double *H, long N, long n, double rho1, double rho2, const double j[3],
+                        double P[3][3])
+{
+    H[0 * N + n] = rho1;
+    H[1 * N + n] = rho2;
+    for (int a = 0; a < 3; ++a) H[(2 + a) * N + n] = j[a];
+    H[5 * N + n] = P[0][0];
+    H[6 * N + n] = P[1][1];
+    H[7 * N + n] = P[2][2];
+    H[8 * N + n] = P[0][1];
+    H[9 * N + n] = P[0][2];
+    H[10 * N + n] = P[1][2];
+}
+
+/* Colour gradient G at node (x,y,z) from the phase field, its norm, and the
+ * unit normal (zero below the threshold). */
+static void colour_gradient(const ora_lat *L, const double *phi, int nx, int ny, int nz, int x, int y,
+                            int z, double G[3], double *Gnorm, double nrm[3])
+{
+    for (int a = 0; a < 3; ++a) G[a] = 0.0;
+    for (int i = 0; i < L->q; ++i) {
+        long nb = ora_neighbour(nx, ny, nz, x, y, z, L->c[i][0], L->c[i][1], L->c[i][2]);
+        for (int a = 0; a < 3; ++a) G[a] += L->w[i] * L->c[i][a] * phi[nb] / ORA_CS2;
+    }
+    *Gnorm = sqrt(G[0] * G[0] + G[1] * G[1] + G[2] * G[2]);
+    for (int a = 0; a < 3; ++a) nrm[a] = *Gnorm > EPS_G ? G[a] / *Gnorm : 0.0;
+    if (!(*Gnorm > EPS_G)) *Gnorm = 0.0;
+}
+
+static double speed(const ora_lat *L, int i)
+{
+    return sqrt((double)(L->c[i][0] * L->c[i][0] + L->c[i][1] * L->c[i][1] + L->c[i][2] * L->c[i][2]));
+}
+
+/* Recolouring term beta (rho1 rho2/rho) w_i (c_i.n)/|c_i| (species 1 sign). */
+static double recolour_term(const ora_lat *L, int i, double beta, double rho1, double rho2,
+                            const double nrm[3])
+{
+    if (i == 0 || speed(L, i) == 0.0) return 0.0;
+    double cn = L->c[i][0] * nrm[0] + L->c[i][1] * nrm[1] + L->c[i][2] * nrm[2];
+    return beta * rho1 * rho2 / (rho1 + rho2) * L->w[i] * cn / speed(L, i);
+}
+
+/* ---- without populations ------------------------------------------------- */
+
+static void cg_moment_step(const ora_lat *L, int nx, int ny, int nz, double omega, double A,
+                           double beta, const double *Hin, double *Hout, double *phi, double *f1post,
+                           double *f2post)
+{
+    long N = (long)nx * ny * nz;
+    int q = L->q;
+
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) phi[n] = (Hin[n] - Hin[N + n]) / (Hin[n] + Hin[N + n]);
+
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long n = (long)x + (long)nx * ((long)y + (long)ny * z);
+                double rho1, rho2, j[3], P[3][3], G[3], Gnorm, nrm[3];
+                double heq[ORA_QMAX], hneq[ORA_QMAX], DP[3][3];
+                load_node2(Hin, N, n, &rho1, &rho2, j, P);
+                double rho = rho1 + rho2;
+                colour_gradient(L, phi, nx, ny, nz, x, y, z, G, &Gnorm, nrm);
+                ora_hermite_parts(L, rho, j, P, heq, hneq);
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        DP[a][b] = A / 9.0 * Gnorm * (nrm[a] * nrm[b] - (a == b ? 1.0 : 0.0));
+                for (int i = 0; i < q; ++i) {
+                    /* Eq. 7, then the reconstructed perturbation w_i Q_i:DP. */
+                    double hpost = (1.0 - omega) * (heq[i] + hneq[i]) + omega * heq[i];
+                    double QDP = 0.0;
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) QDP += ora_Q(L, i, a, b) * DP[a][b];
+                    hpost += L->w[i] * QDP;
+                    double rc = recolour_term(L, i, beta, rho1, rho2, nrm);
+                    f1post[(long)i * N + n] = rho1 / rho * hpost + rc;
+                    f2post[(long)i * N + n] = rho2 / rho * hpost - rc;
+                }
+            }
+
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long n = (long)x + (long)nx * ((long)y + (long)ny * z);
+                double f[ORA_QMAX], rho1 = 0.0, rho2 = 0.0, rho, j[3], P[3][3];
+                for (int i = 0; i < q; ++i) {
+                    long src = ora_neighbour(nx, ny, nz, x, y, z, -L->c[i][0], -L->c[i][1], -L->c[i][2]);
+                    double a1 = f1post[(long)i * N + src], a2 = f2post[(long)i * N + src];
+                    rho1 += a1;
+                    rho2 += a2;
+                    f[i] = a1 + a2;
+                }
+                ora_project(L, f, &rho, j, P);
+                store_node2(Hout, N, n, rho1, rho2, j, P);
+            }
+}
+
+/* Advances the two-component state H (11 fields, in place) by nsteps. */
+int ora_cg_moment_run(int q, int nx, int ny, int nz, double tau, double A, double beta, int nsteps,
+                      double *H)
+{
+    ora_lat L;
+    if (ora_lattice_init(q, &L) != 0 || nx < 1 || ny < 1 || nz < 1 || nsteps < 0) return -1;
+    long N = (long)nx * ny * nz;
+    double *tmp = malloc(sizeof(double) * 11 * N);
+    double *phi = malloc(sizeof(double) * N);
+    double *f1 = malloc(sizeof(double) * q * N);
+    double *f2 = malloc(sizeof(double) * q * N);
+    int rc = 0;
+    if (!tmp || !phi || !f1 || !f2) {
+        rc = -1;
+    } else {
+        for (int t = 0; t < nsteps; ++t) {
+            cg_moment_step(&L, nx, ny, nz, 1.0 / tau, A, beta, H, tmp, phi, f1, f2);
+            memcpy(H, tmp, sizeof(double) * 11 * N);
+        }
+    }
+    free(tmp);
+    free(phi);
+    free(f1);
+    free(f2);
+    return rc;
+}
+
+/* ---- with populations ------------------------------------------------------ */
+
+static void cg_population_step(const ora_lat *L, int nx, int ny, int nz, double omega, double A,
+                               double beta, int regularize, const double *f1in, const double *f2in,
+                               double *f1out, double *f2out, double *phi, double *f1post,
+                               double *f2post)
+{
+    long N = (long)nx * ny * nz;
+    int q = L->q;
+
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) {
+        double r1 = 0.0, r2 = 0.0;
+        for (int i = 0; i < q; ++i) {
+            r1 += f1in[(long)i * N + n];
+            r2 += f2in[(long)i * N + n];
+        }
+        phi[n] = (r1 - r2) / (r1 + r2);
+    }
+
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long n = (long)x + (long)nx * ((long)y + (long)ny * z);
+                double f[ORA_QMAX], rho1 = 0.0, rho2 = 0.0, rho, j[3], P[3][3];
+                double heq[ORA_QMAX], hneq[ORA_QMAX], Df[ORA_QMAX], G[3], Gnorm, nrm[3];
+                for (int i = 0; i < q; ++i) {
+                    rho1 += f1in[(long)i * N + n];
+                    rho2 += f2in[(long)i * N + n];
+                    f[i] = f1in[(long)i * N + n] + f2in[(long)i * N + n];
+                }
+                ora_project(L, f, &rho, j, P);
+                ora_hermite_parts(L, rho, j, P, heq, hneq);
+                colour_gradient(L, phi, nx, ny, nz, x, y, z, G, &Gnorm, nrm);
+
+                /* Perturbation operator, written per population. */
+                for (int i = 0; i < q; ++i) {
+                    double cn = L->c[i][0] * nrm[0] + L->c[i][1] * nrm[1] + L->c[i][2] * nrm[2];
+                    double B = i == 0 ? L->w[0] - 2.0 / 3.0 : L->w[i];
+                    Df[i] = Gnorm > 0.0 ? A / 2.0 * Gnorm * (L->w[i] * cn * cn - B) : 0.0;
+                }
+                if (regularize) {
+                    /* Keep only the Hermite (second-order) part of Df. */
+                    double DP[3][3] = {{0}};
+                    for (int i = 0; i < q; ++i)
+                        for (int a = 0; a < 3; ++a)
+                            for (int b = 0; b < 3; ++b) DP[a][b] += Df[i] * L->c[i][a] * L->c[i][b];
+                    for (int i = 0; i < q; ++i) {
+                        double QDP = 0.0;
+                        for (int a = 0; a < 3; ++a)
+                            for (int b = 0; b < 3; ++b) QDP += ora_Q(L, i, a, b) * DP[a][b];
+                        Df[i] = L->w[i] * QDP;
+                    }
+                }
+                for (int i = 0; i < q; ++i) {
+                    double fi = regularize ? heq[i] + hneq[i] : f[i];
+                    double fpost = (1.0 - omega) * fi + omega * heq[i] + Df[i];
+                    double rc = recolour_term(L, i, beta, rho1, rho2, nrm);
+                    f1post[(long)i * N + n] = rho1 / rho * fpost + rc;
+                    f2post[(long)i * N + n] = rho2 / rho * fpost - rc;
+                }
+            }
+
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long n = (long)x + (long)nx * ((long)y + (long)ny * z);
+                for (int i = 0; i < q; ++i) {
+                    long src = ora_neighbour(nx, ny, nz, x, y, z, -L->c[i][0], -L->c[i][1], -L->c[i][2]);
+                    f1out[(long)i * N + n] = f1post[(long)i * N + src];
+                    f2out[(long)i * N + n] = f2post[(long)i * N + src];
+                }
+            }
+}
+
+/* Advances the species populations f1, f2 (q fields each, in place). */
+int ora_cg_population_run(int q, int nx, int ny, int nz, double tau, double A, double beta,
+                          int regularize, int nsteps, double *f1, double *f2)
+{
+    ora_lat L;
+    if (ora_lattice_init(q, &L) != 0 || nx < 1 || ny < 1 || nz < 1 || nsteps < 0) return -1;
+    long N = (long)nx * ny * nz;
+    double *t1 = malloc(sizeof(double) * q * N);
+    double *t2 = malloc(sizeof(double) * q * N);
+    double *p1 = malloc(sizeof(double) * q * N);
+    double *p2 = malloc(sizeof(double) * q * N);
+    double *phi = malloc(sizeof(double) * N);
+    int rc = 0;
+    if (!t1 || !t2 || !p1 || !p2 || !phi) {
+        rc = -1;
+    } else {
+        for (int t = 0; t < nsteps; ++t) {
+            cg_population_step(&L, nx, ny, nz, 1.0 / tau, A, beta, regularize, f1, f2, t1, t2, phi, p1, p2);
+            memcpy(f1, t1, sizeof(double) * q * N);
+            memcpy(f2, t2, sizeof(double) * q * N);
+        }
+    }
+    free(t1);
+    free(t2);
+    free(p1);
+    free(p2);
+    free(phi);
+    return rc;
+}
