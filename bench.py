@@ -1,0 +1,170 @@
+"""Throughput of the moment-only lattice Boltzmann step on one MI355X.
+
+Workload: 256^3 periodic box, D3Q27, one component, FP32 moments
+(rho, j, P: 10 values per node), tau = 0.6, random solenoidal velocity
+(seed 16220002, max |u| = 1e-3).  A step is one full time step of the
+scheme (one fused kernel launch).  The population-storing BGK scheme is
+timed on the same box and GPU, and the FP64 CPU oracle on the host cores.
+
+Prints one JSON line (see the keys below).  MLUPS follows the paper's
+definition (Sec. III.C): nodes / (1e6 x seconds per step).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % HBM roofline, moment-LB vs population-LB on 1 MI355X; adjoint/forward cost"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "moment_step_256cube_d3q27_f32_traffic.json")
+KERNEL_SOURCES = ["moment_step.hip", "moment_math.hpp", "lattice.hpp", "storage.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2301_01622_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n_nodes: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; otherwise None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash() or t.get("n_nodes") != n_nodes:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def time_steps(sim, stream, steps: int, warmup: int) -> float:
+    import torch
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    sim.step(steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps  # ms per step
+
+
+def cpu_baseline(n: int, q: int, tau: float, steps: int, rho, u):
+    import oracle
+    H = oracle.equilibrium_moments(rho, u)
+    t0 = time.perf_counter()
+    oracle.moment_run(H, q, tau, steps)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": round(n ** 3 * steps / dt / 1e6, 3),
+        "unit": "MLUPS",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{steps} full time steps of the same {n}^3 D3Q27 box (FP64 C oracle, OpenMP, {threads} threads)",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-population", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU halo exchange is a design, not part of this build)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2301_01622_amd import inputs
+    from paper_2301_01622_amd.lbm import LBM
+
+    n, q, tau = args.n, 27, 0.6
+    rho, u = inputs.random_solenoidal_box(n, inputs.SEED_C2, umax=1e-3)
+    rho_d, u_d = torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda()
+    stream = torch.cuda.Stream()
+    N = n ** 3
+
+    with torch.cuda.stream(stream):
+        sim = LBM((n, n, n), q, tau, storage="f32", stream=stream)
+        sim.set_equilibrium(rho_d, u_d)
+        ms = time_steps(sim, stream, args.steps, args.warmup)
+        state_bytes, step_bytes = sim.memory_info()
+        sim.close()
+
+        pop = None
+        if not args.no_population:
+            ps = LBM((n, n, n), q, tau, storage="f32", scheme="population", stream=stream)
+            ps.set_equilibrium(rho_d, u_d)
+            pms = time_steps(ps, stream, args.steps, args.warmup)
+            p_state, p_step = ps.memory_info()
+            ps.close()
+            pop = {
+                "value": round(N / (pms * 1e-3) / 1e6, 1),
+                "unit": "MLUPS",
+                "ms_per_step": round(pms, 5),
+                "hbm_frac": round(p_step / (pms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "bytes_per_node_state": p_state // N,
+            }
+
+    mlups = N / (ms * 1e-3) / 1e6
+    achieved = step_bytes / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(N)
+    line = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{n}^3 periodic box, D3Q27, one component, FP32 moments (rho, j, P), tau=0.6, "
+                        "random solenoidal velocity seed 16220002 max|u|=1e-3",
+            "nodes": N,
+            "lattice": "D3Q27",
+            "storage": "f32",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+        },
+        "bytes_per_node_state": state_bytes // N,
+        "population_lb": pop,
+    }
+    if pop:
+        line["speedup_vs_population_lb"] = round(mlups / pop["value"], 3)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(n, q, tau, args.cpu_steps, rho, u)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,168 @@
+/*
+ * lbm.h -- C ABI of the MI355X lattice Boltzmann library without populations.
+ *
+ * The library advances a lattice Boltzmann fluid whose nodes store only the
+ * hydrodynamic moments H = [rho, rho u_a, P_ab] (Eqs. 1-3 of Tiribocchi et
+ * al., "Lightweight Lattice Boltzmann"), never the populations.  Every time
+ * step rebuilds the populations of each node from its moments with the
+ * second-order Hermite reconstruction (Eq. 4: equilibrium part Eq. 5 plus
+ * non-equilibrium part Eq. 6, ghosts dropped), relaxes them with BGK
+ * (Eqs. 7-8), streams them by pulling from the neighbours (Eq. 9) and stores
+ * the moments of the streamed set (Eqs. 1-3) in a second copy of the arrays
+ * (the flip-flop pair of Sec. III.A).  Two-component fluids follow the
+ * colour-gradient model the paper uses (Sec. III.A): one density per species
+ * on a shared momentum and pressure tensor, with perturbation and
+ * recolouring applied after the collision.
+ *
+ * For comparison the same context can instead run a conventional
+ * population-storing BGK scheme (LBM_SCHEME_POPULATION), the "LB with
+ * populations" of Sec. IV.
+ *
+ * Conventions shared by every entry point
+ *   - Box: nx*ny*nz nodes, fully periodic, node index n = x + nx*(y + ny*z).
+ *   - Lattice: D3Q19 (the paper's) or D3Q27, c_s^2 = 1/3, nu = c_s^2 (tau - 1/2).
+ *   - Public moment layout (lbm_fields): structure of arrays, field k starts
+ *     at base + k*field_stride elements, each field holds N = nx*ny*nz
+ *     contiguous values.  Field order:
+ *       one species : rho, jx, jy, jz, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz   (10)
+ *       two species : rho1, rho2, jx, jy, jz, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz (11)
+ *     with j = rho u the momentum density and P the full second moment.
+ *     The moments are the post-streaming (pre-collision) ones.
+ *   - All calls are asynchronous on the context's HIP stream unless stated.
+ *     A context is not thread-safe; use one per stream.
+ *   - Errors: every int-returning call returns LBM_OK (0) or a negative
+ *     LBM_E* code; lbm_last_error() then holds a message.  No call aborts the
+ *     process and no C++ exception crosses this interface.
+ *   - Ownership: the library owns the context and every buffer it allocates;
+ *     buffers passed in lbm_fields stay owned by the caller.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ----------------------------------------------------------------- */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)    /* bad argument (size, lattice, tau <= 1/2, ...) */
+#define LBM_ENOMEM (-2)    /* device allocation failed */
+#define LBM_EDEVICE (-3)   /* a HIP call failed; text in lbm_last_error */
+#define LBM_EUNSTABLE (-4) /* a global FP64 check found a non-finite mass or momentum */
+#define LBM_ESTATE (-5)    /* call not valid for this context (scheme, species, ...) */
+
+/* ---- schemes and storage formats ------------------------------------------------- */
+#define LBM_SCHEME_MOMENT 0     /* the paper's method: moments only (default) */
+#define LBM_SCHEME_POPULATION 1 /* population-storing BGK, A-B buffers (baseline) */
+
+/* Device storage of the moment state.  All formats store deviations from the
+ * rest state rho = 1, u = 0: delta_rho = rho - 1, j, and
+ * S = (P - rho c_s^2 I) * s_pi; two-component states store delta_rho of the
+ * mixture and rho1.  Arithmetic is FP64 for LBM_STORE_F64 and FP32 otherwise. */
+#define LBM_STORE_F64 0
+#define LBM_STORE_F32 1
+#define LBM_STORE_F16 2  /* IEEE binary16, round to nearest even */
+#define LBM_STORE_BF16 3 /* bfloat16, round to nearest even */
+
+/* Element types of caller buffers. */
+#define LBM_DTYPE_F64 0
+#define LBM_DTYPE_F32 1
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef struct {
+    int nx, ny, nz; /* each >= 3 */
+} lbm_grid;
+
+typedef struct {
+    int scheme;      /* LBM_SCHEME_*; default LBM_SCHEME_MOMENT */
+    int storage;     /* LBM_STORE_*; default LBM_STORE_F32 (population scheme: F32 or F64) */
+    double beta;     /* recolouring strength, two species; default 0.7 */
+    double sigma;    /* surface tension, two species; default 0.01 (A = 9 sigma / (2 tau)) */
+    double s_pi;     /* scale of the stored S; 0 = default (1024 for F16, 1 otherwise) */
+    void *stream;    /* hipStream_t to run on; NULL = the null stream */
+    int device;      /* HIP device ordinal; -1 = current device */
+    int check_every; /* lbm_step runs the FP64 check every this many steps; 0 = never */
+} lbm_opts;
+
+/* Caller-owned moment buffers, see the layout above. */
+typedef struct {
+    void *base;           /* first element of field 0 */
+    int64_t field_stride; /* elements between the starts of consecutive fields (>= N) */
+    int dtype;            /* LBM_DTYPE_F32 or LBM_DTYPE_F64 */
+    int on_device;        /* 1: device memory of the context's device; 0: host memory */
+} lbm_fields;
+
+/* Fills *opts with the defaults listed above.  NULL-safe. */
+void lbm_default_opts(lbm_opts *opts);
+
+/* Creates a context: validates the arguments, allocates the two state copies
+ * (flip-flop, Sec. III.A) on the device and initialises the fluid at rest
+ * (rho = 1, u = 0, P = c_s^2 I; species 1 fills the box).
+ *   grid    : box size, every side >= 3
+ *   lattice : 19 or 27
+ *   tau     : BGK relaxation time (Eq. 7, omega = 1/tau), > 1/2
+ *   species : 1, or 2 for the colour-gradient mixture (moment scheme, D3Q19
+ *             or D3Q27, FP32/FP64 storage)
+ *   opts    : NULL for the defaults
+ * On success *out holds the context; on failure *out is NULL.
+ * Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE. */
+int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int species, const lbm_opts *opts);
+
+/* Frees the context and everything the library allocated.  NULL-safe.
+ * Synchronises the stream first. */
+int lbm_destroy(lbm_ctx *ctx);
+
+/* Replaces the state by the given moments (public layout above; the moments
+ * are post-streaming ones).  For the population scheme the populations are
+ * rebuilt from them with Eq. 4.  Host buffers are copied before return.
+ * Errors: LBM_EINVAL (NULL, bad dtype or stride), LBM_EDEVICE. */
+int lbm_set_moments(lbm_ctx *ctx, const lbm_fields *in);
+
+/* Writes the current moments (Eqs. 1-3 of the post-streaming set) to a
+ * caller buffer in the public layout.  Synchronises the stream when the
+ * destination is host memory.  Errors: LBM_EINVAL, LBM_EDEVICE. */
+int lbm_get_moments(const lbm_ctx *ctx, lbm_fields *out);
+
+/* Sets an equilibrium state from primitive fields: the buffer holds
+ * rho (one species) or rho1, rho2 (two species) followed by ux, uy, uz; the
+ * moments become rho^k, j = rho u and P = rho c_s^2 I + rho u u (the second
+ * moment of Eq. 5), i.e. a zero non-equilibrium part.
+ * Errors: LBM_EINVAL, LBM_EDEVICE. */
+int lbm_set_equilibrium(lbm_ctx *ctx, const lbm_fields *primitive);
+
+/* Advances n >= 0 time steps (one fused kernel launch per step for the moment
+ * scheme).  Asynchronous unless check_every > 0, in which case the FP64 check
+ * of lbm_reduce runs every check_every steps and the call returns
+ * LBM_EUNSTABLE at the first non-finite total.  Errors: LBM_EINVAL,
+ * LBM_EDEVICE, LBM_EUNSTABLE. */
+int lbm_step(lbm_ctx *ctx, int n);
+
+/* Global totals in FP64, summed on the device in a fixed order:
+ * out[0] = sum rho (species 1 for two species), out[1] = sum rho2 (0 for one
+ * species), out[2..4] = sum j.  Synchronises the stream.
+ * Returns LBM_EUNSTABLE if any total is not finite. */
+int lbm_reduce(lbm_ctx *ctx, double out[5]);
+
+/* Bytes of device memory the context holds for its state (both copies) and
+ * the bytes one time step moves at minimum (every stored value read once and
+ * written once).  Either pointer may be NULL. */
+int lbm_memory_info(const lbm_ctx *ctx, int64_t *state_bytes, int64_t *step_bytes);
+
+/* Number of time steps advanced since creation or the last set_* call. */
+int64_t lbm_steps_done(const lbm_ctx *ctx);
+
+/* Static description of an error code; never NULL. */
+const char *lbm_strerror(int code);
+
+/* Message of the last failed call on this context ("" if none); never NULL,
+ * valid until the next call on the context.  NULL-safe. */
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,339 @@
+// C ABI of the library (declared and documented in include/lbm.h).
+//
+// Host-side only: argument validation, device buffers, stream binding and
+// error reporting.  Every step of the method runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+namespace {
+
+int fail(const lbm_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(const lbm_ctx *c, hipError_t e, const char *where)
+{
+    std::string m = std::string(where) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return fail(c, LBM_ENOMEM, m);
+    return fail(c, LBM_EDEVICE, m);
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (dev >= 0 && dev != prev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+size_t storage_bytes(int storage)
+{
+    switch (storage) {
+    case LBM_STORE_F64: return 8;
+    case LBM_STORE_F32: return 4;
+    case LBM_STORE_F16:
+    case LBM_STORE_BF16: return 2;
+    default: return 0;
+    }
+}
+
+int check_fields(const lbm_ctx *c, const lbm_fields *f, int nfields)
+{
+    if (!f || !f->base) return fail(c, LBM_EINVAL, "fields: NULL buffer");
+    if (f->dtype != LBM_DTYPE_F32 && f->dtype != LBM_DTYPE_F64) return fail(c, LBM_EINVAL, "fields: bad dtype");
+    if (f->field_stride < c->N) return fail(c, LBM_EINVAL, "fields: field_stride < number of nodes");
+    (void)nfields;
+    return LBM_OK;
+}
+
+// Copies a caller buffer to a fresh device buffer when it is on the host.
+// *dev receives a device pointer with the same layout; *owned is set when the
+// caller must free it.
+int stage_in(const lbm_ctx *c, const lbm_fields *f, int nfields, const void **dev, void **owned)
+{
+    *owned = nullptr;
+    if (f->on_device) {
+        *dev = f->base;
+        return LBM_OK;
+    }
+    const size_t bytes = (size_t)(f->dtype == LBM_DTYPE_F64 ? 8 : 4) * (size_t)f->field_stride * (size_t)nfields;
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMalloc(staging)");
+    e = hipMemcpyAsync(d, f->base, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(c, e, "hipMemcpyAsync(host->device)");
+    }
+    *dev = d;
+    *owned = d;
+    return LBM_OK;
+}
+
+int public_fields(const lbm_ctx *c) { return c->species == 1 ? 10 : 11; }
+
+} // namespace
+
+extern "C" {
+
+void lbm_default_opts(lbm_opts *o)
+{
+    if (!o) return;
+    o->scheme = LBM_SCHEME_MOMENT;
+    o->storage = LBM_STORE_F32;
+    o->beta = 0.7;
+    o->sigma = 0.01;
+    o->s_pi = 0.0;
+    o->stream = nullptr;
+    o->device = -1;
+    o->check_every = 0;
+}
+
+const char *lbm_strerror(int code)
+{
+    switch (code) {
+    case LBM_OK: return "success";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "out of device memory";
+    case LBM_EDEVICE: return "HIP runtime error";
+    case LBM_EUNSTABLE: return "non-finite global mass or momentum (unstable run)";
+    case LBM_ESTATE: return "operation not valid for this context";
+    default: return "unknown error";
+    }
+}
+
+const char *lbm_last_error(const lbm_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int species, const lbm_opts *opts)
+{
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    lbm_opts o;
+    lbm_default_opts(&o);
+    if (opts) o = *opts;
+    if (grid.nx < 3 || grid.ny < 3 || grid.nz < 3) return LBM_EINVAL;
+    if (lattice != 19 && lattice != 27) return LBM_EINVAL;
+    if (!(tau > 0.5) || !std::isfinite(tau)) return LBM_EINVAL;
+    if (species != 1 && species != 2) return LBM_EINVAL;
+    if (o.scheme != LBM_SCHEME_MOMENT && o.scheme != LBM_SCHEME_POPULATION) return LBM_EINVAL;
+    if (storage_bytes(o.storage) == 0) return LBM_EINVAL;
+    if (o.check_every < 0) return LBM_EINVAL;
+    if (o.scheme == LBM_SCHEME_POPULATION && o.storage != LBM_STORE_F32 && o.storage != LBM_STORE_F64)
+        return LBM_EINVAL;
+    if (species == 2 && o.storage != LBM_STORE_F32 && o.storage != LBM_STORE_F64) return LBM_EINVAL;
+    if (species == 2 && (!(o.beta >= 0.0) || !(o.sigma >= 0.0))) return LBM_EINVAL;
+    if (!(o.s_pi >= 0.0) || !std::isfinite(o.s_pi)) return LBM_EINVAL;
+    if (species == 2 && o.scheme == LBM_SCHEME_POPULATION) return LBM_EINVAL;
+    if (species == 2) return LBM_EINVAL;  // two-species kernels are not built yet
+
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return LBM_ENOMEM;
+    c->nx = grid.nx;
+    c->ny = grid.ny;
+    c->nz = grid.nz;
+    c->N = (int64_t)grid.nx * grid.ny * grid.nz;
+    c->q = lattice;
+    c->species = species;
+    c->scheme = o.scheme;
+    c->storage = o.storage;
+    c->tau = tau;
+    c->omega = 1.0 / tau;
+    c->beta = o.beta;
+    c->sigma = o.sigma;
+    c->A = 9.0 * o.sigma / (2.0 * tau);
+    c->s_pi = o.s_pi > 0.0 ? o.s_pi : (o.storage == LBM_STORE_F16 ? 1024.0 : 1.0);
+    c->stream = static_cast<hipStream_t>(o.stream);
+    c->check_every = o.check_every;
+    c->elem = storage_bytes(o.storage);
+    c->nfields = o.scheme == LBM_SCHEME_MOMENT ? (species == 1 ? 10 : 11) : lattice * species;
+
+    if (o.device >= 0) {
+        c->device = o.device;
+    } else if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return LBM_EDEVICE;
+    }
+    DeviceGuard g(c->device);
+    const size_t bytes = c->elem * (size_t)c->nfields * (size_t)c->N;
+    for (int k = 0; k < 2; ++k) {
+        hipError_t e = hipMalloc(&c->state[k], bytes);
+        if (e != hipSuccess) {
+            lbm_destroy(c);
+            return e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE;
+        }
+    }
+    if (hipMalloc((void **)&c->partials, sizeof(double) * 5 * lbm::kReduceBlocks) != hipSuccess ||
+        hipMalloc((void **)&c->red_out, sizeof(double) * 5) != hipSuccess) {
+        lbm_destroy(c);
+        return LBM_ENOMEM;
+    }
+    // Fluid at rest: every stored deviation is zero (species 1 fills the box,
+    // so rho1 = 1 for two species).
+    for (int k = 0; k < 2; ++k) {
+        if (hipMemsetAsync(c->state[k], 0, bytes, c->stream) != hipSuccess) {
+            lbm_destroy(c);
+            return LBM_EDEVICE;
+        }
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+        lbm_destroy(c);
+        return LBM_EDEVICE;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx *c)
+{
+    if (!c) return LBM_OK;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < 2; ++k)
+        if (c->state[k]) (void)hipFree(c->state[k]);
+    if (c->partials) (void)hipFree(c->partials);
+    if (c->red_out) (void)hipFree(c->red_out);
+    delete c;
+    return LBM_OK;
+}
+
+int lbm_set_moments(lbm_ctx *c, const lbm_fields *in)
+{
+    if (!c) return LBM_EINVAL;
+    c->err.clear();
+    const int nf = public_fields(c);
+    int rc = check_fields(c, in, nf);
+    if (rc) return rc;
+    DeviceGuard g(c->device);
+    const void *dev = nullptr;
+    void *owned = nullptr;
+    if ((rc = stage_in(c, in, nf, &dev, &owned))) return rc;
+    hipError_t e = lbm::launch_set_moments(c, dev, in->field_stride, in->dtype, c->state[c->cur]);
+    if (owned) {
+        hipError_t e2 = hipStreamSynchronize(c->stream);
+        (void)hipFree(owned);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "set_moments");
+    c->steps = 0;
+    return LBM_OK;
+}
+
+int lbm_set_equilibrium(lbm_ctx *c, const lbm_fields *prim)
+{
+    if (!c) return LBM_EINVAL;
+    c->err.clear();
+    const int nf = c->species + 3;
+    int rc = check_fields(c, prim, nf);
+    if (rc) return rc;
+    DeviceGuard g(c->device);
+    const void *dev = nullptr;
+    void *owned = nullptr;
+    if ((rc = stage_in(c, prim, nf, &dev, &owned))) return rc;
+    hipError_t e = lbm::launch_set_equilibrium(c, dev, prim->field_stride, prim->dtype, c->state[c->cur]);
+    if (owned) {
+        hipError_t e2 = hipStreamSynchronize(c->stream);
+        (void)hipFree(owned);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "set_equilibrium");
+    c->steps = 0;
+    return LBM_OK;
+}
+
+int lbm_get_moments(const lbm_ctx *c, lbm_fields *out)
+{
+    if (!c) return LBM_EINVAL;
+    c->err.clear();
+    const int nf = public_fields(c);
+    int rc = check_fields(c, out, nf);
+    if (rc) return rc;
+    DeviceGuard g(c->device);
+    if (out->on_device) {
+        hipError_t e = lbm::launch_get_moments(c, c->state[c->cur], out->base, out->field_stride, out->dtype);
+        if (e != hipSuccess) return hip_fail(c, e, "get_moments");
+        return LBM_OK;
+    }
+    const size_t bytes = (size_t)(out->dtype == LBM_DTYPE_F64 ? 8 : 4) * (size_t)out->field_stride * (size_t)nf;
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMalloc(staging)");
+    e = lbm::launch_get_moments(c, c->state[c->cur], d, out->field_stride, out->dtype);
+    if (e == hipSuccess) e = hipMemcpyAsync(out->base, d, bytes, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(c, e, "get_moments(host)");
+    return LBM_OK;
+}
+
+int lbm_reduce(lbm_ctx *c, double out[5])
+{
+    if (!c || !out) return LBM_EINVAL;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    hipError_t e = lbm::launch_reduce(c, c->state[c->cur]);
+    double v[5];
+    if (e == hipSuccess) e = hipMemcpyAsync(v, c->red_out, sizeof(v), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reduce");
+    const double n = (double)c->N;
+    if (c->species == 1) {
+        out[0] = n + v[0];
+        out[1] = 0.0;
+    } else {
+        out[0] = v[0];
+        out[1] = n + v[1] - v[0];
+    }
+    for (int a = 0; a < 3; ++a) out[2 + a] = v[2 + a];
+    for (int k = 0; k < 5; ++k)
+        if (!std::isfinite(out[k])) return fail(c, LBM_EUNSTABLE, "non-finite global total");
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int n)
+{
+    if (!c || n < 0) return fail(c, LBM_EINVAL, "lbm_step: bad argument");
+    c->err.clear();
+    DeviceGuard g(c->device);
+    for (int t = 0; t < n; ++t) {
+        const void *in = c->state[c->cur];
+        void *out = c->state[1 - c->cur];
+        hipError_t e = c->scheme == LBM_SCHEME_MOMENT ? lbm::launch_moment_step(c, in, out)
+                                                      : lbm::launch_population_step(c, in, out);
+        if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
+        c->cur = 1 - c->cur;
+        ++c->steps;
+        if (c->check_every > 0 && c->steps % c->check_every == 0) {
+            double tot[5];
+            int rc = lbm_reduce(c, tot);
+            if (rc) return rc;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_memory_info(const lbm_ctx *c, int64_t *state_bytes, int64_t *step_bytes)
+{
+    if (!c) return LBM_EINVAL;
+    const int64_t per_copy = (int64_t)c->elem * c->nfields * c->N;
+    if (state_bytes) *state_bytes = 2 * per_copy;
+    if (step_bytes) *step_bytes = 2 * per_copy;
+    return LBM_OK;
+}
+
+int64_t lbm_steps_done(const lbm_ctx *c) { return c ? c->steps : -1; }
+
+} // extern "C"

@@ -1,0 +1,339 @@
+// Conversions between caller moment buffers and the stored state, and the
+// FP64 global totals.
+//
+// Public layout: field k of a caller buffer starts at base + k*stride; fields
+// are (rho | rho1, rho2), jx, jy, jz, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz.
+// Stored moment state: delta_rho, [rho1], j, S * s_pi with S = P - rho/3 I.
+// Stored population state (pull scheme): post-collision shifted populations
+// f~_i = f_i - w_i, so that the populations arriving at x are f~_i(x - c_i).
+// Conversions run in FP64 whatever the storage; only the final store rounds.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "moment_math.hpp"
+#include "storage.hpp"
+
+namespace lbm {
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+// ---- moment scheme -------------------------------------------------------------
+
+template <class S, class T>
+__global__ void k_set_moment_state(const T *__restrict__ src, int64_t stride, S *__restrict__ st, int64_t N,
+                                   int species, double s_pi)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    double rho, rho1 = 0.0;
+    int off;
+    if (species == 1) {
+        rho = (double)src[n];
+        off = 1;
+    } else {
+        rho1 = (double)src[n];
+        rho = rho1 + (double)src[stride + n];
+        off = 2;
+    }
+    const int js = species == 1 ? 1 : 2;  // first stored j field
+    st[n] = Store<S>::make((typename Store<S>::real)(rho - 1.0));
+    if (species == 2) st[N + n] = Store<S>::make((typename Store<S>::real)rho1);
+    for (int a = 0; a < 3; ++a)
+        st[(js + a) * N + n] = Store<S>::make((typename Store<S>::real)src[(off + a) * stride + n]);
+    for (int k = 0; k < 6; ++k) {
+        double p = (double)src[(off + 3 + k) * stride + n];
+        if (k < 3) p -= rho / 3.0;
+        st[(js + 3 + k) * N + n] = Store<S>::make((typename Store<S>::real)(p * s_pi));
+    }
+}
+
+template <class S, class T>
+__global__ void k_get_moment_state(const S *__restrict__ st, T *__restrict__ dst, int64_t stride, int64_t N,
+                                   int species, double inv_s_pi)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const double rho = 1.0 + (double)Store<S>::load(st[n]);
+    const int js = species == 1 ? 1 : 2;
+    int off;
+    if (species == 1) {
+        dst[n] = (T)rho;
+        off = 1;
+    } else {
+        const double rho1 = (double)Store<S>::load(st[N + n]);
+        dst[n] = (T)rho1;
+        dst[stride + n] = (T)(rho - rho1);
+        off = 2;
+    }
+    for (int a = 0; a < 3; ++a) dst[(off + a) * stride + n] = (T)(double)Store<S>::load(st[(js + a) * N + n]);
+    for (int k = 0; k < 6; ++k) {
+        double p = (double)Store<S>::load(st[(js + 3 + k) * N + n]) * inv_s_pi;
+        if (k < 3) p += rho / 3.0;
+        dst[(off + 3 + k) * stride + n] = (T)p;
+    }
+}
+
+// ---- population scheme -------------------------------------------------------------
+
+// A_i[y] = shifted R(M(y + c_i))_i (Eq. 4 without collision).
+template <int Q, class S, class T>
+__global__ void k_set_population_state(const T *__restrict__ src, int64_t stride, S *__restrict__ A, int nx,
+                                       int ny, int nz, int64_t N)
+{
+    using L = Lattice<Q>;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int x = (int)(n % nx);
+    const int64_t t = n / nx;
+    const int y = (int)(t % ny), z = (int)(t / ny);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int xs = (x + L::cx(i) + nx) % nx, ys = (y + L::cy(i) + ny) % ny, zs = (z + L::cz(i) + nz) % nz;
+        const int64_t s = (int64_t)xs + (int64_t)nx * ((int64_t)ys + (int64_t)ny * zs);
+        const double rho = (double)src[s];
+        Collided<double> p;
+        p.jx = (double)src[stride + s];
+        p.jy = (double)src[2 * stride + s];
+        p.jz = (double)src[3 * stride + s];
+        p.sxx = (double)src[4 * stride + s] - rho / 3.0;
+        p.syy = (double)src[5 * stride + s] - rho / 3.0;
+        p.szz = (double)src[6 * stride + s] - rho / 3.0;
+        p.sxy = (double)src[7 * stride + s];
+        p.sxz = (double)src[8 * stride + s];
+        p.syz = (double)src[9 * stride + s];
+        p.T = (rho - 1.0) - 1.5 * (p.sxx + p.syy + p.szz);
+        A[(int64_t)i * N + n] = Store<S>::make((typename Store<S>::real)reconstruct<Q, double>(p, i));
+    }
+}
+
+// Moments of the populations arriving at x, f~_i = A_i[x - c_i].
+template <int Q, class S, class T>
+__global__ void k_get_population_state(const S *__restrict__ A, T *__restrict__ dst, int64_t stride, int nx,
+                                       int ny, int nz, int64_t N)
+{
+    using L = Lattice<Q>;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int x = (int)(n % nx);
+    const int64_t t = n / nx;
+    const int y = (int)(t % ny), z = (int)(t / ny);
+    MomentAcc<double> a;
+    a.zero();
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int xs = (x - L::cx(i) + nx) % nx, ys = (y - L::cy(i) + ny) % ny, zs = (z - L::cz(i) + nz) % nz;
+        const int64_t s = (int64_t)xs + (int64_t)nx * ((int64_t)ys + (int64_t)ny * zs);
+        accumulate<Q, double>(a, (double)Store<S>::load(A[(int64_t)i * N + s]), i);
+    }
+    const double rho = 1.0 + a.r;
+    dst[n] = (T)rho;
+    dst[stride + n] = (T)a.jx;
+    dst[2 * stride + n] = (T)a.jy;
+    dst[3 * stride + n] = (T)a.jz;
+    dst[4 * stride + n] = (T)(a.mxx + 1.0 / 3.0);
+    dst[5 * stride + n] = (T)(a.myy + 1.0 / 3.0);
+    dst[6 * stride + n] = (T)(a.mzz + 1.0 / 3.0);
+    dst[7 * stride + n] = (T)a.mxy;
+    dst[8 * stride + n] = (T)a.mxz;
+    dst[9 * stride + n] = (T)a.myz;
+}
+
+// ---- primitive fields -> equilibrium moments (public layout, FP64) -------------
+
+template <class T>
+__global__ void k_primitive_to_moments(const T *__restrict__ src, int64_t stride, double *__restrict__ pub,
+                                       int64_t N, int species)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    double rho;
+    int off;
+    if (species == 1) {
+        rho = (double)src[n];
+        pub[n] = rho;
+        off = 1;
+    } else {
+        const double r1 = (double)src[n], r2 = (double)src[stride + n];
+        rho = r1 + r2;
+        pub[n] = r1;
+        pub[N + n] = r2;
+        off = 2;
+    }
+    double u[3];
+    for (int a = 0; a < 3; ++a) u[a] = (double)src[(off + a) * stride + n];
+    for (int a = 0; a < 3; ++a) pub[(off + a) * N + n] = rho * u[a];
+    const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
+    for (int k = 0; k < 6; ++k)
+        pub[(off + 3 + k) * N + n] = rho * u[pa[k]] * u[pb[k]] + (k < 3 ? rho / 3.0 : 0.0);
+}
+
+// ---- FP64 totals -------------------------------------------------------------------
+
+// Block-level deterministic tree sum of 5 values per thread.
+__device__ void block_sum5(double v[5], double *out)
+{
+    __shared__ double sh[5][kThreads];
+    for (int k = 0; k < 5; ++k) sh[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 5; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 5; ++k) out[k] = sh[k][0];
+}
+
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_reduce_moment(const S *__restrict__ st, int64_t N, int species,
+                                                            double *__restrict__ partials)
+{
+    double v[5] = {0, 0, 0, 0, 0};
+    const int js = species == 1 ? 1 : 2;
+    for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < N; n += (int64_t)gridDim.x * kThreads) {
+        if (species == 1) {
+            v[0] += (double)Store<S>::load(st[n]);
+        } else {
+            v[0] += (double)Store<S>::load(st[N + n]);
+            v[1] += (double)Store<S>::load(st[n]);
+        }
+        for (int a = 0; a < 3; ++a) v[2 + a] += (double)Store<S>::load(st[(js + a) * N + n]);
+    }
+    block_sum5(v, partials + 5 * blockIdx.x);
+}
+
+template <int Q, class S>
+__global__ __launch_bounds__(kThreads) void k_reduce_population(const S *__restrict__ A, int64_t N,
+                                                                double *__restrict__ partials)
+{
+    using L = Lattice<Q>;
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < N; n += (int64_t)gridDim.x * kThreads) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double f = (double)Store<S>::load(A[(int64_t)i * N + n]);
+            v[0] += f;
+            v[2] += L::cx(i) * f;
+            v[3] += L::cy(i) * f;
+            v[4] += L::cz(i) * f;
+        }
+    }
+    block_sum5(v, partials + 5 * blockIdx.x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce_final(const double *__restrict__ partials, int nblocks,
+                                                           double *__restrict__ out)
+{
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += kThreads)
+        for (int k = 0; k < 5; ++k) v[k] += partials[5 * b + k];
+    block_sum5(v, out);
+}
+
+// ---- dispatch helpers -----------------------------------------------------------------
+
+template <class F>
+hipError_t with_storage(const lbm_ctx *c, F &&f)
+{
+    switch (c->storage) {
+    case LBM_STORE_F64: return f((double *)nullptr);
+    case LBM_STORE_F32: return f((float *)nullptr);
+    case LBM_STORE_F16: return f((f16 *)nullptr);
+    case LBM_STORE_BF16: return f((bf16 *)nullptr);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+} // namespace
+
+hipError_t launch_set_moments(const lbm_ctx *c, const void *src, int64_t stride, int dtype, void *state)
+{
+    return with_storage(c, [&](auto *tag) -> hipError_t {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        auto go = [&](auto *ttag) -> hipError_t {
+            using T = std::remove_pointer_t<decltype(ttag)>;
+            const T *s = static_cast<const T *>(src);
+            if (c->scheme == LBM_SCHEME_MOMENT) {
+                hipLaunchKernelGGL((k_set_moment_state<S, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
+                                   s, stride, static_cast<S *>(state), c->N, c->species, c->s_pi);
+            } else if (c->q == 19) {
+                hipLaunchKernelGGL((k_set_population_state<19, S, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0,
+                                   c->stream, s, stride, static_cast<S *>(state), c->nx, c->ny, c->nz, c->N);
+            } else {
+                hipLaunchKernelGGL((k_set_population_state<27, S, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0,
+                                   c->stream, s, stride, static_cast<S *>(state), c->nx, c->ny, c->nz, c->N);
+            }
+            return hipGetLastError();
+        };
+        return dtype == LBM_DTYPE_F64 ? go((double *)nullptr) : go((float *)nullptr);
+    });
+}
+
+hipError_t launch_get_moments(const lbm_ctx *c, const void *state, void *dst, int64_t stride, int dtype)
+{
+    return with_storage(c, [&](auto *tag) -> hipError_t {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        auto go = [&](auto *ttag) -> hipError_t {
+            using T = std::remove_pointer_t<decltype(ttag)>;
+            T *d = static_cast<T *>(dst);
+            const S *st = static_cast<const S *>(state);
+            if (c->scheme == LBM_SCHEME_MOMENT) {
+                hipLaunchKernelGGL((k_get_moment_state<S, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
+                                   st, d, stride, c->N, c->species, 1.0 / c->s_pi);
+            } else if (c->q == 19) {
+                hipLaunchKernelGGL((k_get_population_state<19, S, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0,
+                                   c->stream, st, d, stride, c->nx, c->ny, c->nz, c->N);
+            } else {
+                hipLaunchKernelGGL((k_get_population_state<27, S, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0,
+                                   c->stream, st, d, stride, c->nx, c->ny, c->nz, c->N);
+            }
+            return hipGetLastError();
+        };
+        return dtype == LBM_DTYPE_F64 ? go((double *)nullptr) : go((float *)nullptr);
+    });
+}
+
+hipError_t launch_set_equilibrium(const lbm_ctx *c, const void *src, int64_t stride, int dtype, void *state)
+{
+    const int nf = c->species == 1 ? 10 : 11;
+    double *pub = nullptr;
+    hipError_t e = hipMallocAsync((void **)&pub, sizeof(double) * nf * c->N, c->stream);
+    if (e != hipSuccess) return e;
+    if (dtype == LBM_DTYPE_F64)
+        hipLaunchKernelGGL((k_primitive_to_moments<double>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
+                           static_cast<const double *>(src), stride, pub, c->N, c->species);
+    else
+        hipLaunchKernelGGL((k_primitive_to_moments<float>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
+                           static_cast<const float *>(src), stride, pub, c->N, c->species);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = launch_set_moments(c, pub, c->N, LBM_DTYPE_F64, state);
+    hipError_t e2 = hipFreeAsync(pub, c->stream);
+    return e != hipSuccess ? e : e2;
+}
+
+hipError_t launch_reduce(const lbm_ctx *c, const void *state)
+{
+    hipError_t e = with_storage(c, [&](auto *tag) -> hipError_t {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        const S *st = static_cast<const S *>(state);
+        if (c->scheme == LBM_SCHEME_MOMENT)
+            hipLaunchKernelGGL((k_reduce_moment<S>), dim3(kReduceBlocks), dim3(kThreads), 0, c->stream, st, c->N,
+                               c->species, c->partials);
+        else if (c->q == 19)
+            hipLaunchKernelGGL((k_reduce_population<19, S>), dim3(kReduceBlocks), dim3(kThreads), 0, c->stream, st,
+                               c->N, c->partials);
+        else
+            hipLaunchKernelGGL((k_reduce_population<27, S>), dim3(kReduceBlocks), dim3(kThreads), 0, c->stream, st,
+                               c->N, c->partials);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kThreads), 0, c->stream, c->partials, kReduceBlocks,
+                       c->red_out);
+    return hipGetLastError();
+}
+
+} // namespace lbm

@@ -1,0 +1,50 @@
+// Library-internal context and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "lbm.h"
+
+struct lbm_ctx {
+    int nx = 0, ny = 0, nz = 0;
+    int64_t N = 0;
+    int q = 19, species = 1, scheme = LBM_SCHEME_MOMENT, storage = LBM_STORE_F32;
+    double tau = 1.0, omega = 1.0, beta = 0.7, sigma = 0.0, A = 0.0, s_pi = 1.0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int check_every = 0;
+    int nfields = 0;  // stored arrays per state copy
+    size_t elem = 4;  // bytes per stored element
+    void *state[2] = {nullptr, nullptr};
+    int cur = 0;      // state[cur] holds the current time level
+    double *partials = nullptr;  // FP64 reduction partials (kReduceBlocks x 5)
+    double *red_out = nullptr;   // 5 device doubles
+    int64_t steps = 0;
+    mutable std::string err;
+};
+
+namespace lbm {
+
+constexpr int kReduceBlocks = 1024;
+
+// Moment scheme.
+hipError_t launch_moment_step(const lbm_ctx *c, const void *in, void *out);
+
+// Population scheme.
+hipError_t launch_population_step(const lbm_ctx *c, const void *in, void *out);
+
+// Conversions between the public moment layout (dtype F32/F64, device
+// pointer, given field stride) and the stored state of either scheme.
+hipError_t launch_set_moments(const lbm_ctx *c, const void *src, int64_t stride, int dtype, void *state);
+hipError_t launch_get_moments(const lbm_ctx *c, const void *state, void *dst, int64_t stride, int dtype);
+hipError_t launch_set_equilibrium(const lbm_ctx *c, const void *src, int64_t stride, int dtype, void *state);
+
+// FP64 totals of the stored state into c->red_out (device, 5 doubles):
+// sum of delta_rho (one species) or rho1, sum of delta_rho (two species)
+// or 0, sum of j.  The host adds N where the state stores deviations.
+hipError_t launch_reduce(const lbm_ctx *c, const void *state);
+
+} // namespace lbm

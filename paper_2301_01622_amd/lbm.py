@@ -1,0 +1,145 @@
+"""Python handle on the C-ABI library: device memory and streams via PyTorch.
+
+``LBM`` wraps one ``lbm_ctx``.  Moment tensors use the public layout of
+include/lbm.h: shape (nfields, nz, ny, nx), x fastest, fields
+(rho | rho1, rho2), jx, jy, jz, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz, with j = rho u.
+Every computation runs in the library's HIP kernels; this module only passes
+pointers, sizes and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+
+
+class LBM:
+    """One periodic box advanced by the moment-only scheme (or, with
+    scheme="population", by the population-storing baseline)."""
+
+    def __init__(self, shape, lattice: int = 19, tau: float = 0.8, species: int = 1, *,
+                 scheme: str = "moment", storage: str = "f32", beta: float = 0.7, sigma: float = 0.01,
+                 s_pi: float = 0.0, device: int = 0, stream: torch.cuda.Stream | None = None,
+                 check_every: int = 0):
+        lib = _lib.load()
+        self.nx, self.ny, self.nz = (int(s) for s in shape)
+        self.q, self.tau, self.species = int(lattice), float(tau), int(species)
+        self.scheme, self.storage = scheme, storage
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        opts = _lib.Opts()
+        lib.lbm_default_opts(ctypes.byref(opts))
+        opts.scheme = _lib.SCHEME[scheme]
+        opts.storage = _lib.STORAGE[storage]
+        opts.beta = beta
+        opts.sigma = sigma
+        opts.s_pi = s_pi
+        opts.stream = ctypes.c_void_p(self.stream.cuda_stream)
+        opts.device = device
+        opts.check_every = check_every
+        ctx = ctypes.c_void_p()
+        rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(self.nx, self.ny, self.nz), self.q, self.tau,
+                            self.species, ctypes.byref(opts))
+        _lib.check(rc, None, "lbm_create")
+        self._ctx = ctx
+        self._lib = lib
+
+    # ---- properties -------------------------------------------------------
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def nfields(self) -> int:
+        return 10 if self.species == 1 else 11
+
+    @property
+    def n_nodes(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    # ---- state ------------------------------------------------------------
+    def _fields(self, t) -> _lib.Fields:
+        if isinstance(t, torch.Tensor):
+            assert t.is_contiguous() and t.dtype in (torch.float32, torch.float64)
+            assert t.numel() % self.n_nodes == 0
+            on_dev = 1 if t.is_cuda else 0
+            return _lib.Fields(t.data_ptr(), self.n_nodes,
+                               _lib.DTYPE_F64 if t.dtype == torch.float64 else _lib.DTYPE_F32, on_dev)
+        a = t
+        assert isinstance(a, np.ndarray) and a.flags.c_contiguous and a.dtype in (np.float32, np.float64)
+        return _lib.Fields(a.ctypes.data, self.n_nodes,
+                           _lib.DTYPE_F64 if a.dtype == np.float64 else _lib.DTYPE_F32, 0)
+
+    def set_moments(self, M) -> None:
+        """M: (nfields, nz, ny, nx) float32/float64, torch (any device) or numpy."""
+        assert tuple(M.shape) == (self.nfields,) + self.shape, M.shape
+        if isinstance(M, torch.Tensor) and M.is_cuda:
+            M = M.contiguous()
+        f = self._fields(M)
+        _lib.check(self._lib.lbm_set_moments(self._ctx, ctypes.byref(f)), self._ctx, "set_moments")
+        if isinstance(M, torch.Tensor) and M.is_cuda:
+            self._keepalive = M  # the conversion may still be pending on the stream
+
+    def set_equilibrium(self, rho, u) -> None:
+        """rho: (nz,ny,nx) or (2,nz,ny,nx) for two species; u: (3,nz,ny,nx)."""
+        if isinstance(rho, np.ndarray):
+            prim = np.ascontiguousarray(np.concatenate([np.reshape(rho, (-1,) + self.shape), u], axis=0))
+        else:
+            prim = torch.cat([rho.reshape((-1,) + self.shape), u], dim=0).contiguous()
+        assert prim.shape[0] == self.species + 3
+        f = self._fields(prim)
+        _lib.check(self._lib.lbm_set_equilibrium(self._ctx, ctypes.byref(f)), self._ctx, "set_equilibrium")
+        if isinstance(prim, torch.Tensor) and prim.is_cuda:
+            self._keepalive = prim  # the copy may still be pending on the stream
+
+    def get_moments(self, dtype=torch.float64, device: str = "cuda") -> torch.Tensor:
+        """Current (post-streaming) moments in the public layout."""
+        dev = self.device if device == "cuda" else torch.device("cpu")
+        out = torch.empty((self.nfields,) + self.shape, dtype=dtype, device=dev)
+        if dev.type == "cpu":
+            out = out.pin_memory() if torch.cuda.is_available() else out
+        f = self._fields(out)
+        _lib.check(self._lib.lbm_get_moments(self._ctx, ctypes.byref(f)), self._ctx, "get_moments")
+        return out
+
+    # ---- time stepping ---------------------------------------------------
+    def step(self, n: int = 1) -> None:
+        _lib.check(self._lib.lbm_step(self._ctx, int(n)), self._ctx, "step")
+
+    def reduce(self) -> np.ndarray:
+        """FP64 totals: sum rho (rho1), sum rho2, sum j."""
+        out = (ctypes.c_double * 5)()
+        _lib.check(self._lib.lbm_reduce(self._ctx, out), self._ctx, "reduce")
+        return np.array(out[:])
+
+    def memory_info(self):
+        """(state bytes for both copies, minimum bytes moved per step)."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(self._lib.lbm_memory_info(self._ctx, ctypes.byref(a), ctypes.byref(b)), self._ctx)
+        return a.value, b.value
+
+    @property
+    def steps_done(self) -> int:
+        return int(self._lib.lbm_steps_done(self._ctx))
+
+    def close(self) -> None:
+        if getattr(self, "_ctx", None):
+            self._lib.lbm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

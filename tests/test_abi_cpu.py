@@ -1,0 +1,62 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, it
+exports every entry point include/lbm.h declares, and argument validation
+rejects bad input before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2301_01622_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(lbm_\w+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    declared = _declared()
+    assert {"lbm_create", "lbm_step", "lbm_get_moments", "lbm_set_moments", "lbm_reduce",
+            "lbm_destroy"} <= declared
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+
+
+def test_error_strings_and_null_safety():
+    lib = _lib.load()
+    for code in (_lib.LBM_OK, _lib.LBM_EINVAL, _lib.LBM_ENOMEM, _lib.LBM_EDEVICE, _lib.LBM_EUNSTABLE,
+                 _lib.LBM_ESTATE, -99):
+        assert lib.lbm_strerror(code)
+    assert lib.lbm_last_error(None) == b""
+    assert lib.lbm_destroy(None) == _lib.LBM_OK
+    assert lib.lbm_steps_done(None) == -1
+
+
+@pytest.mark.parametrize("grid,q,tau,species,scheme,storage", [
+    ((2, 8, 8), 19, 0.8, 1, 0, 1),     # side < 3
+    ((8, 8, 8), 15, 0.8, 1, 0, 1),     # unknown lattice
+    ((8, 8, 8), 19, 0.5, 1, 0, 1),     # tau must exceed 1/2
+    ((8, 8, 8), 19, float("nan"), 1, 0, 1),
+    ((8, 8, 8), 19, 0.8, 3, 0, 1),     # species
+    ((8, 8, 8), 19, 0.8, 1, 7, 1),     # scheme
+    ((8, 8, 8), 19, 0.8, 1, 0, 9),     # storage
+    ((8, 8, 8), 19, 0.8, 1, 1, 2),     # population scheme stores F32/F64 only
+])
+def test_create_rejects_bad_arguments_before_device(grid, q, tau, species, scheme, storage):
+    lib = _lib.load()
+    opts = _lib.Opts()
+    lib.lbm_default_opts(ctypes.byref(opts))
+    opts.scheme, opts.storage = scheme, storage
+    ctx = ctypes.c_void_p(123)
+    rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(*grid), q, tau, species, ctypes.byref(opts))
+    assert rc == _lib.LBM_EINVAL
+    assert not ctx.value
