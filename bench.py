@@ -86,6 +86,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-population", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--calibrate-copy", type=int, default=10,
+                    help="also time this many state copies (plain copy kernel of known size)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -107,6 +109,22 @@ def main() -> int:
         sim.set_equilibrium(rho_d, u_d)
         ms = time_steps(sim, stream, args.steps, args.warmup)
         state_bytes, step_bytes = sim.memory_info()
+        copy = None
+        if args.calibrate_copy > 0:
+            buf = sim.new_checkpoint()
+            sim.save_state(buf)
+            torch.cuda.synchronize()
+            c0 = torch.cuda.Event(enable_timing=True)
+            c1 = torch.cuda.Event(enable_timing=True)
+            c0.record(stream)
+            for _ in range(args.calibrate_copy):
+                sim.save_state(buf)
+            c1.record(stream)
+            torch.cuda.synchronize()
+            cms = c0.elapsed_time(c1) / args.calibrate_copy
+            copy = {"bytes_per_launch": 2 * sim.state_bytes, "ms": round(cms, 5),
+                    "gbs": round(2 * sim.state_bytes / (cms * 1e-3) / 1e9, 1)}
+            del buf
         sim.close()
 
         pop = None
@@ -156,8 +174,11 @@ def main() -> int:
             "traffic": traffic,
         },
         "bytes_per_node_state": state_bytes // N,
+        "copy_kernel": copy,
         "population_lb": pop,
     }
+    if copy:
+        line["roofline"]["frac_of_measured_copy"] = round(achieved / copy["gbs"], 4)
     if pop:
         line["speedup_vs_population_lb"] = round(mlups / pop["value"], 3)
     if not args.no_cpu_baseline:

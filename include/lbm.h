@@ -151,6 +151,18 @@ int lbm_reduce(lbm_ctx *ctx, double out[5]);
  * written once).  Either pointer may be NULL. */
 int lbm_memory_info(const lbm_ctx *ctx, int64_t *state_bytes, int64_t *step_bytes);
 
+/* Size in bytes of one time level of the stored state (the buffer that
+ * lbm_save_state fills).  Errors: LBM_EINVAL. */
+int lbm_state_bytes(const lbm_ctx *ctx, int64_t *bytes);
+
+/* Copies the current time level of the stored state, in its storage format,
+ * to / from a caller-owned device buffer of lbm_state_bytes() bytes with the
+ * library's streaming copy kernel (used for the adjoint's checkpoints).
+ * Asynchronous on the context's stream; a restored state continues bit for
+ * bit like the saved one.  Errors: LBM_EINVAL (NULL), LBM_EDEVICE. */
+int lbm_save_state(lbm_ctx *ctx, void *dst_device);
+int lbm_load_state(lbm_ctx *ctx, const void *src_device);
+
 /* Number of time steps advanced since creation or the last set_* call. */
 int64_t lbm_steps_done(const lbm_ctx *ctx);
 

@@ -80,6 +80,9 @@ def load() -> ctypes.CDLL:
         "lbm_step": (c_int, [c_void, c_int]),
         "lbm_reduce": (c_int, [c_void, P(c_dbl)]),
         "lbm_memory_info": (c_int, [c_void, P(ctypes.c_int64), P(ctypes.c_int64)]),
+        "lbm_state_bytes": (c_int, [c_void, P(ctypes.c_int64)]),
+        "lbm_save_state": (c_int, [c_void, c_void]),
+        "lbm_load_state": (c_int, [c_void, c_void]),
         "lbm_steps_done": (ctypes.c_int64, [c_void]),
         "lbm_strerror": (ctypes.c_char_p, [c_int]),
         "lbm_last_error": (ctypes.c_char_p, [c_void]),

@@ -334,6 +334,35 @@ int lbm_memory_info(const lbm_ctx *c, int64_t *state_bytes, int64_t *step_bytes)
     return LBM_OK;
 }
 
+int lbm_state_bytes(const lbm_ctx *c, int64_t *bytes)
+{
+    if (!c || !bytes) return LBM_EINVAL;
+    *bytes = (int64_t)c->elem * c->nfields * c->N;
+    return LBM_OK;
+}
+
+int lbm_save_state(lbm_ctx *c, void *dst)
+{
+    if (!c) return LBM_EINVAL;
+    if (!dst) return fail(c, LBM_EINVAL, "save_state: NULL buffer");
+    c->err.clear();
+    DeviceGuard g(c->device);
+    hipError_t e = lbm::launch_copy(c, c->state[c->cur], dst, (int64_t)c->elem * c->nfields * c->N);
+    if (e != hipSuccess) return hip_fail(c, e, "save_state");
+    return LBM_OK;
+}
+
+int lbm_load_state(lbm_ctx *c, const void *src)
+{
+    if (!c) return LBM_EINVAL;
+    if (!src) return fail(c, LBM_EINVAL, "load_state: NULL buffer");
+    c->err.clear();
+    DeviceGuard g(c->device);
+    hipError_t e = lbm::launch_copy(c, src, c->state[c->cur], (int64_t)c->elem * c->nfields * c->N);
+    if (e != hipSuccess) return hip_fail(c, e, "load_state");
+    return LBM_OK;
+}
+
 int64_t lbm_steps_done(const lbm_ctx *c) { return c ? c->steps : -1; }
 
 } // extern "C"

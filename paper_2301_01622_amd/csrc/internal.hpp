@@ -42,6 +42,9 @@ hipError_t launch_set_moments(const lbm_ctx *c, const void *src, int64_t stride,
 hipError_t launch_get_moments(const lbm_ctx *c, const void *state, void *dst, int64_t stride, int dtype);
 hipError_t launch_set_equilibrium(const lbm_ctx *c, const void *src, int64_t stride, int dtype, void *state);
 
+// Streaming device-to-device copy of `bytes` bytes (16-byte vector accesses).
+hipError_t launch_copy(const lbm_ctx *c, const void *src, void *dst, int64_t bytes);
+
 // FP64 totals of the stored state into c->red_out (device, 5 doubles):
 // sum of delta_rho (one species) or rho1, sum of delta_rho (two species)
 // or 0, sum of j.  The host adds N where the state stores deviations.

@@ -11,6 +11,11 @@
 // are again deviations: sum h~ = dr', sum c h~ = j',
 // sum c_a c_b h~ - (dr'/3) delta_ab = S'_new.  Every quantity is small, so
 // FP32 arithmetic and 16-bit storage keep their relative precision.
+//
+// Both the reconstruction and the moment sums are organised by velocity
+// layers c_z = -1, 0, +1: within a layer the nine (c_x, c_y) combinations
+// share partial sums, which roughly halves the arithmetic of writing every
+// direction out on its own.
 #pragma once
 
 #include "lattice.hpp"
@@ -24,11 +29,23 @@ struct Collided {
 };
 
 template <class R>
+__device__ __forceinline__ R reciprocal(R x)
+{
+    return R(1) / x;
+}
+// FP32: the hardware reciprocal (1 ulp); 1/rho only scales the O(u^2) term.
+template <>
+__device__ __forceinline__ float reciprocal<float>(float x)
+{
+    return __builtin_amdgcn_rcpf(x);
+}
+
+template <class R>
 __device__ __forceinline__ Collided<R> collide(R dr, R jx, R jy, R jz, R sxx, R syy, R szz, R sxy, R sxz,
                                                R syz, R omega)
 {
     Collided<R> p;
-    const R inv_rho = R(1) / (R(1) + dr);
+    const R inv_rho = reciprocal<R>(R(1) + dr);
     const R om1 = R(1) - omega;
     const R ox = omega * inv_rho * jx, oy = omega * inv_rho * jy, oz = omega * inv_rho * jz;
     p.sxx = om1 * sxx + ox * jx;
@@ -44,7 +61,8 @@ __device__ __forceinline__ Collided<R> collide(R dr, R jx, R jy, R jz, R sxx, R 
     return p;
 }
 
-// Shifted population h~_i of direction i (compile-time after unrolling).
+// Shifted population h~_i of direction i written out on its own (used by
+// the conversion kernels; the step kernels use the layered form below).
 template <int Q, class R>
 __device__ __forceinline__ R reconstruct(const Collided<R> &p, int i)
 {
@@ -62,6 +80,62 @@ __device__ __forceinline__ R reconstruct(const Collided<R> &p, int i)
     if (cx * cz != 0) quad += (cx * cz > 0 ? R(2) : R(-2)) * p.sxz;
     if (cy * cz != 0) quad += (cy * cz > 0 ? R(2) : R(-2)) * p.syz;
     return R(L::w(i)) * (lin + R(4.5) * quad);
+}
+
+// The nine (c_x, c_y) slots of one layer, index (cx+1) + 3 (cy+1).
+template <class R>
+struct Layer {
+    R v[9];
+};
+
+// Does the lattice contain direction (cx, cy, cz)?
+template <int Q>
+__host__ __device__ constexpr bool has_dir(int cx, int cy, int cz)
+{
+    return Q == 27 || (cx * cx + cy * cy + cz * cz) <= 2;
+}
+
+template <int Q>
+__host__ __device__ constexpr double weight(int cx, int cy, int cz)
+{
+    if (Q == 27) return Lattice<27>::w1(cx) * Lattice<27>::w1(cy) * Lattice<27>::w1(cz);
+    const int s = cx * cx + cy * cy + cz * cz;
+    return s == 0 ? 1.0 / 3.0 : s == 1 ? 1.0 / 18.0 : s == 2 ? 1.0 / 36.0 : 0.0;
+}
+
+// Shifted populations of layer c_z = CZ.  With
+//   A  = T + 3 cz jz + 4.5 cz^2 Szz,  Bx = 3 jx + 9 cz Sxz,  By = 3 jy + 9 cz Syz,
+// the bracket is A + cx Bx + cy By + 4.5 (cx^2 Sxx + cy^2 Syy) + 9 cx cy Sxy.
+// Slots of directions absent from the lattice are left unset.
+template <int Q, int CZ, class R>
+__device__ __forceinline__ void reconstruct_layer(const Collided<R> &p, Layer<R> &o)
+{
+    const R jx3 = R(3) * p.jx, jy3 = R(3) * p.jy;
+    R A, Bx, By;
+    if (CZ == 0) {
+        A = p.T;
+        Bx = jx3;
+        By = jy3;
+    } else {
+        A = p.T + R(4.5) * p.szz + R(3 * CZ) * p.jz;
+        Bx = jx3 + R(9 * CZ) * p.sxz;
+        By = jy3 + R(9 * CZ) * p.syz;
+    }
+    const R xx = R(4.5) * p.sxx, yy = R(4.5) * p.syy;
+    const R Px = A + xx, Py = A + yy;
+    o.v[4] = R(weight<Q>(0, 0, CZ)) * A;
+    o.v[5] = R(weight<Q>(1, 0, CZ)) * (Px + Bx);
+    o.v[3] = R(weight<Q>(-1, 0, CZ)) * (Px - Bx);
+    o.v[7] = R(weight<Q>(0, 1, CZ)) * (Py + By);
+    o.v[1] = R(weight<Q>(0, -1, CZ)) * (Py - By);
+    if (has_dir<Q>(1, 1, CZ)) {
+        const R Pxy = Px + yy, s9 = R(9) * p.sxy;
+        const R D1 = Pxy + s9, D2 = Pxy - s9, E1 = Bx + By, E2 = Bx - By;
+        o.v[8] = R(weight<Q>(1, 1, CZ)) * (D1 + E1);
+        o.v[0] = R(weight<Q>(-1, -1, CZ)) * (D1 - E1);
+        o.v[2] = R(weight<Q>(1, -1, CZ)) * (D2 + E2);
+        o.v[6] = R(weight<Q>(-1, 1, CZ)) * (D2 - E2);
+    }
 }
 
 // Moment accumulators of the streamed shifted set (Eqs. 1-3).
@@ -86,6 +160,47 @@ __device__ __forceinline__ void accumulate(MomentAcc<R> &a, R h, int i)
     if (cx * cy != 0) { if (cx * cy > 0) a.mxy += h; else a.mxy -= h; }
     if (cx * cz != 0) { if (cx * cz > 0) a.mxz += h; else a.mxz -= h; }
     if (cy * cz != 0) { if (cy * cz > 0) a.myz += h; else a.myz -= h; }
+}
+
+// Adds the streamed populations of layer c_z = CZ (slots as in Layer) to
+// the accumulators of their destination plane.  Rows of fixed c_y are
+// summed first (sum, sum c_x, sum c_x^2), then the rows are combined.
+template <int Q, int CZ, class R>
+__device__ __forceinline__ void accumulate_layer(MomentAcc<R> &a, const Layer<R> &f)
+{
+    constexpr bool corners = has_dir<Q>(1, 1, CZ);
+    // Row c_y = 0: slots 3 (cx=-1), 4 (cx=0), 5 (cx=+1).
+    const R r0_2 = f.v[3] + f.v[5], r0_1 = f.v[5] - f.v[3], r0_0 = r0_2 + f.v[4];
+    R s, sx, sy, sxx, syy, sxy;
+    if (corners) {
+        // Rows c_y = -1 (slots 0,1,2) and +1 (slots 6,7,8).
+        const R rm_2 = f.v[0] + f.v[2], rm_1 = f.v[2] - f.v[0], rm_0 = rm_2 + f.v[1];
+        const R rp_2 = f.v[6] + f.v[8], rp_1 = f.v[8] - f.v[6], rp_0 = rp_2 + f.v[7];
+        syy = rp_0 + rm_0;
+        s = syy + r0_0;
+        sy = rp_0 - rm_0;
+        sx = r0_1 + (rp_1 + rm_1);
+        sxy = rp_1 - rm_1;
+        sxx = r0_2 + (rp_2 + rm_2);
+    } else {
+        syy = f.v[7] + f.v[1];
+        s = syy + r0_0;
+        sy = f.v[7] - f.v[1];
+        sx = r0_1;
+        sxy = R(0);
+        sxx = r0_2;
+    }
+    a.r += s;
+    a.jx += sx;
+    a.jy += sy;
+    a.mxx += sxx;
+    a.myy += syy;
+    if (corners) a.mxy += sxy;
+    if (CZ != 0) {
+        if (CZ > 0) { a.jz += s; a.mxz += sx; a.myz += sy; }
+        else { a.jz -= s; a.mxz -= sx; a.myz -= sy; }
+        a.mzz += s;
+    }
 }
 
 } // namespace lbm

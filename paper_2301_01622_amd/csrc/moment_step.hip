@@ -24,6 +24,8 @@
 // block of tiles, keeping halo re-reads inside one L2.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.hpp"
 #include "moment_math.hpp"
 #include "storage.hpp"
@@ -53,6 +55,35 @@ __device__ __forceinline__ void load_moments(const S *__restrict__ in, int64_t N
     for (int k = 0; k < 10; ++k) m.v[k] = Store<S>::load(in[k * N + idx]);
 }
 
+template <class S>
+__device__ __forceinline__ void store_out(S *p, S v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+template <>
+__device__ __forceinline__ void store_out<bf16>(bf16 *p, bf16 v)
+{
+    __builtin_nontemporal_store(v.bits, reinterpret_cast<uint16_t *>(p));
+}
+
+// LDS slot of direction (slot, layer CZ), slot = (cx+1) + 3 (cy+1); the
+// own-column slot 4 never goes through LDS.  Directions absent from the
+// lattice get no slot.  Returns -1 for "no slot".
+template <int Q>
+__host__ __device__ constexpr int lds_slot(int cz, int slot)
+{
+    int k = 0;
+    for (int z = -1; z <= 1; ++z)
+        for (int sl = 0; sl < 9; ++sl) {
+            if (sl == 4 || !has_dir<Q>(sl % 3 - 1, sl / 3 - 1, z)) continue;
+            if (z == cz && sl == slot) return k;
+            ++k;
+        }
+    return -1;
+}
+template <int Q>
+constexpr int kLdsSlots = Q - 3;
+
 template <int Q, class S, int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in, S *__restrict__ out, TileGrid g,
                                                         typename Store<S>::real omega,
@@ -60,11 +91,12 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
                                                         typename Store<S>::real inv_s_pi)
 {
     using R = typename Store<S>::real;
-    using L = Lattice<Q>;
+    constexpr bool kScaled = sizeof(S) == 2;  // 16-bit storage keeps S * s_pi
     constexpr int NT = TX * TY;
     constexpr int HX = TX + 2, HY = TY + 2, HN = HX * HY;
-    constexpr int NSRC = (HN + NT - 1) / NT;  // source nodes per thread
-    __shared__ R lds[Q * HN];
+    constexpr int RING = HN - NT;             // halo nodes around the tile
+    static_assert(RING <= NT, "halo ring must fit one pass");
+    __shared__ R lds[kLdsSlots<Q> * HN];
 
     // XCD-aware tile numbering (falls back to the identity when the grid
     // does not split evenly over the XCDs).
@@ -84,56 +116,95 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
     const bool active = (x0 + lx < g.nx) && (y0 + ly < g.ny);
     const int h0 = (ly + 1) * HX + (lx + 1);  // this thread's interior slot
 
-    // xy offsets of this thread's source nodes (periodic wrap done once).
-    int64_t src_xy[NSRC];
-    bool src_ok[NSRC];
-#pragma unroll
-    for (int k = 0; k < NSRC; ++k) {
-        const int h = tid + k * NT;
-        src_ok[k] = h < HN;
+    // Source nodes: pass 0 is the thread's own interior node, pass 1 a node
+    // of the halo ring (threads tid < RING).  Periodic wrap is done once.
+    const bool has_ring = tid < RING;
+    int hr;
+    {
+        const int m = tid;
+        int hx, hy;
+        if (m < HX) { hx = m; hy = 0; }
+        else if (m < 2 * HX) { hx = m - HX; hy = HY - 1; }
+        else if (m < 2 * HX + TY) { hx = 0; hy = 1 + (m - 2 * HX); }
+        else { hx = HX - 1; hy = 1 + (m - 2 * HX - TY); }
+        hr = hy * HX + hx;
+    }
+    auto wrap_xy = [&](int h) -> int64_t {
         const int hx = h % HX, hy = h / HX;
         int gx = (x0 - 1 + hx) % g.nx, gy = (y0 - 1 + hy) % g.ny;
         gx += gx < 0 ? g.nx : 0;
         gy += gy < 0 ? g.ny : 0;
-        src_xy[k] = (int64_t)gx + (int64_t)g.nx * gy;
-    }
+        return (int64_t)gx + (int64_t)g.nx * gy;
+    };
+    const int64_t own_xy = wrap_xy(h0);
+    const int64_t ring_xy = has_ring ? wrap_xy(hr) : 0;
 
     MomentAcc<R> acc[3];
     acc[0].zero();
     acc[1].zero();
     acc[2].zero();
 
-    Moments<R> m[NSRC];
-    auto fetch = [&](int p) {
-        int zs = p < 0 ? p + g.nz : (p >= g.nz ? p - g.nz : p);
-#pragma unroll
-        for (int k = 0; k < NSRC; ++k)
-            if (src_ok[k]) load_moments<S>(in, g.N, src_xy[k] + (int64_t)zs * plane, m[k]);
+    // Two register sets of source moments: while plane p is collided from
+    // one, the loads of plane p+1 (issued a full plane earlier) land in the
+    // other.
+    Moments<R> own_a, own_b, ring_a, ring_b;
+    auto fetch = [&](int p, Moments<R> &own, Moments<R> &ring) {
+        const int zs = p < 0 ? p + g.nz : (p >= g.nz ? p - g.nz : p);
+        load_moments<S>(in, g.N, own_xy + (int64_t)zs * plane, own);
+        if (has_ring) load_moments<S>(in, g.N, ring_xy + (int64_t)zs * plane, ring);
     };
 
-    fetch(z0 - 1);
-    for (int p = z0 - 1; p <= z_end; ++p) {
-        // Collide each source node once and publish its populations.
-#pragma unroll
-        for (int k = 0; k < NSRC; ++k) {
-            if (!src_ok[k]) continue;
-            const Moments<R> &v = m[k];
-            const Collided<R> c = collide<R>(v.v[0], v.v[1], v.v[2], v.v[3], v.v[4] * inv_s_pi, v.v[5] * inv_s_pi,
-                                             v.v[6] * inv_s_pi, v.v[7] * inv_s_pi, v.v[8] * inv_s_pi,
-                                             v.v[9] * inv_s_pi, omega);
-            const int h = tid + k * NT;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) lds[i * HN + h] = reconstruct<Q, R>(c, i);
-        }
-        __syncthreads();
-        if (p < z_end) fetch(p + 1);
+    auto collide_node = [&](const Moments<R> &v) {
+        if (kScaled)
+            return collide<R>(v.v[0], v.v[1], v.v[2], v.v[3], v.v[4] * inv_s_pi, v.v[5] * inv_s_pi,
+                              v.v[6] * inv_s_pi, v.v[7] * inv_s_pi, v.v[8] * inv_s_pi, v.v[9] * inv_s_pi, omega);
+        return collide<R>(v.v[0], v.v[1], v.v[2], v.v[3], v.v[4], v.v[5], v.v[6], v.v[7], v.v[8], v.v[9], omega);
+    };
 
-        // Pull: direction i arrives from (x - c_i); cz selects the plane.
+    // Writes the populations of one source node into LDS slot h; returns the
+    // node's own-column values (slot 4 of each layer) through `own4`.
+    auto publish = [&](const Collided<R> &c, int h, R *own4) {
+        Layer<R> L0, L1, L2;
+        reconstruct_layer<Q, -1, R>(c, L0);
+        reconstruct_layer<Q, 0, R>(c, L1);
+        reconstruct_layer<Q, 1, R>(c, L2);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const R h = lds[i * HN + h0 - L::cy(i) * HX - L::cx(i)];
-            accumulate<Q, R>(acc[L::cz(i) + 1], h, i);
+        for (int sl = 0; sl < 9; ++sl) {
+            if (lds_slot<Q>(-1, sl) >= 0) lds[lds_slot<Q>(-1, sl) * HN + h] = L0.v[sl];
+            if (lds_slot<Q>(0, sl) >= 0) lds[lds_slot<Q>(0, sl) * HN + h] = L1.v[sl];
+            if (lds_slot<Q>(1, sl) >= 0) lds[lds_slot<Q>(1, sl) * HN + h] = L2.v[sl];
         }
+        if (own4) {
+            own4[0] = L0.v[4];
+            own4[1] = L1.v[4];
+            own4[2] = L2.v[4];
+        }
+    };
+
+    // Gathers layer CZ of the populations streaming into this thread's node.
+    auto pull_layer = [&](auto czc, R own) {
+        constexpr int CZ = decltype(czc)::value;
+        Layer<R> f;
+#pragma unroll
+        for (int sl = 0; sl < 9; ++sl) {
+            const int cx = sl % 3 - 1, cy = sl / 3 - 1;
+            if (sl == 4) f.v[sl] = own;
+            else if (lds_slot<Q>(CZ, sl) >= 0) f.v[sl] = lds[lds_slot<Q>(CZ, sl) * HN + h0 - cy * HX - cx];
+        }
+        accumulate_layer<Q, CZ, R>(acc[CZ + 1], f);
+    };
+
+    auto plane_step = [&](int p, Moments<R> &own_m, Moments<R> &ring_m) {
+        R own4[3];
+        publish(collide_node(own_m), h0, own4);
+        if (has_ring) publish(collide_node(ring_m), hr, nullptr);
+        __syncthreads();
+        if (p + 2 <= z_end) fetch(p + 2, own_m, ring_m);
+
+        // Pull: direction c arrives from (x - c); layer cz feeds plane p + cz.
+        pull_layer(std::integral_constant<int, -1>(), own4[0]);
+        pull_layer(std::integral_constant<int, 0>(), own4[1]);
+        pull_layer(std::integral_constant<int, 1>(), own4[2]);
         __syncthreads();
 
         // Plane p-1 has now received from p-2, p-1 and p.
@@ -142,28 +213,42 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
             const int64_t o = (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)d * plane;
             const MomentAcc<R> &a = acc[0];
             const R third = a.r * R(1.0 / 3.0);
-            out[o] = Store<S>::make(a.r);
-            out[g.N + o] = Store<S>::make(a.jx);
-            out[2 * g.N + o] = Store<S>::make(a.jy);
-            out[3 * g.N + o] = Store<S>::make(a.jz);
-            out[4 * g.N + o] = Store<S>::make((a.mxx - third) * s_pi);
-            out[5 * g.N + o] = Store<S>::make((a.myy - third) * s_pi);
-            out[6 * g.N + o] = Store<S>::make((a.mzz - third) * s_pi);
-            out[7 * g.N + o] = Store<S>::make(a.mxy * s_pi);
-            out[8 * g.N + o] = Store<S>::make(a.mxz * s_pi);
-            out[9 * g.N + o] = Store<S>::make(a.myz * s_pi);
+            const R sc = kScaled ? s_pi : R(1);
+            store_out(out + o, Store<S>::make(a.r));
+            store_out(out + g.N + o, Store<S>::make(a.jx));
+            store_out(out + 2 * g.N + o, Store<S>::make(a.jy));
+            store_out(out + 3 * g.N + o, Store<S>::make(a.jz));
+            store_out(out + 4 * g.N + o, Store<S>::make(kScaled ? (a.mxx - third) * sc : a.mxx - third));
+            store_out(out + 5 * g.N + o, Store<S>::make(kScaled ? (a.myy - third) * sc : a.myy - third));
+            store_out(out + 6 * g.N + o, Store<S>::make(kScaled ? (a.mzz - third) * sc : a.mzz - third));
+            store_out(out + 7 * g.N + o, Store<S>::make(kScaled ? a.mxy * sc : a.mxy));
+            store_out(out + 8 * g.N + o, Store<S>::make(kScaled ? a.mxz * sc : a.mxz));
+            store_out(out + 9 * g.N + o, Store<S>::make(kScaled ? a.myz * sc : a.myz));
         }
         acc[0] = acc[1];
         acc[1] = acc[2];
         acc[2].zero();
+    };
+
+    fetch(z0 - 1, own_a, ring_a);
+    fetch(z0, own_b, ring_b);
+    for (int p = z0 - 1; p <= z_end; p += 2) {
+        plane_step(p, own_a, ring_a);
+        if (p + 1 <= z_end) plane_step(p + 1, own_b, ring_b);
     }
 }
 
-// Chunk length along z: aim for about four resident waves of workgroups on
-// 256 CUs while keeping the two recomputed halo planes a small fraction.
+// Chunk length along z.  Each chunk re-reads two halo planes that the
+// neighbouring chunk also reads, at another time and usually on another XCD,
+// so the re-read costs HBM bandwidth: chunks are made as long as possible
+// while still giving about one resident round of workgroups (two per CU on
+// 256 CUs).
+#ifndef LBM_TARGET_BLOCKS
+#define LBM_TARGET_BLOCKS 512
+#endif
 inline int choose_zchunk(int nz, int tiles_xy)
 {
-    const int target_blocks = 2048;
+    const int target_blocks = LBM_TARGET_BLOCKS;
     int chunks = (target_blocks + tiles_xy - 1) / tiles_xy;
     if (chunks < 1) chunks = 1;
     int zc = (nz + chunks - 1) / chunks;

@@ -124,6 +124,27 @@ class LBM:
         return a.value, b.value
 
     @property
+    def state_bytes(self) -> int:
+        """Bytes of one time level of the stored state."""
+        b = ctypes.c_int64()
+        _lib.check(self._lib.lbm_state_bytes(self._ctx, ctypes.byref(b)), self._ctx, "state_bytes")
+        return b.value
+
+    def new_checkpoint(self) -> torch.Tensor:
+        """A device buffer able to hold one saved time level."""
+        return torch.empty(self.state_bytes, dtype=torch.uint8, device=self.device)
+
+    def save_state(self, buf: torch.Tensor) -> None:
+        """Copies the current stored state into `buf` (device, state_bytes)."""
+        assert buf.is_cuda and buf.numel() * buf.element_size() >= self.state_bytes
+        _lib.check(self._lib.lbm_save_state(self._ctx, ctypes.c_void_p(buf.data_ptr())), self._ctx, "save_state")
+
+    def load_state(self, buf: torch.Tensor) -> None:
+        """Restores a state saved by save_state (same context shape/storage)."""
+        assert buf.is_cuda and buf.numel() * buf.element_size() >= self.state_bytes
+        _lib.check(self._lib.lbm_load_state(self._ctx, ctypes.c_void_p(buf.data_ptr())), self._ctx, "load_state")
+
+    @property
     def steps_done(self) -> int:
         return int(self._lib.lbm_steps_done(self._ctx))
 
