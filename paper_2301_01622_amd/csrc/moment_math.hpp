@@ -20,7 +20,24 @@
 
 #include "lattice.hpp"
 
+// Every fused multiply-add below is written out: with implicit contraction
+// the compiler may fuse the same expression differently at two inlined call
+// sites (e.g. a node collided as a tile node and as a halo node), and the
+// result would then depend on the tiling.
+#pragma clang fp contract(off)
+
 namespace lbm {
+
+template <class R>
+__device__ __forceinline__ R fma_(R a, R b, R c)
+{
+    return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fma_<float>(float a, float b, float c)
+{
+    return __builtin_fmaf(a, b, c);
+}
 
 // Post-collision moments of one node, ready for reconstruction.
 template <class R>
@@ -47,14 +64,15 @@ __device__ __forceinline__ Collided<R> collide(R dr, R jx, R jy, R jz, R sxx, R 
     Collided<R> p;
     const R inv_rho = reciprocal<R>(R(1) + dr);
     const R om1 = R(1) - omega;
-    const R ox = omega * inv_rho * jx, oy = omega * inv_rho * jy, oz = omega * inv_rho * jz;
-    p.sxx = om1 * sxx + ox * jx;
-    p.syy = om1 * syy + oy * jy;
-    p.szz = om1 * szz + oz * jz;
-    p.sxy = om1 * sxy + ox * jy;
-    p.sxz = om1 * sxz + ox * jz;
-    p.syz = om1 * syz + oy * jz;
-    p.T = dr - R(1.5) * (p.sxx + p.syy + p.szz);
+    const R oi = omega * inv_rho;
+    const R ox = oi * jx, oy = oi * jy, oz = oi * jz;
+    p.sxx = fma_(ox, jx, om1 * sxx);
+    p.syy = fma_(oy, jy, om1 * syy);
+    p.szz = fma_(oz, jz, om1 * szz);
+    p.sxy = fma_(ox, jy, om1 * sxy);
+    p.sxz = fma_(ox, jz, om1 * sxz);
+    p.syz = fma_(oy, jz, om1 * syz);
+    p.T = fma_(R(-1.5), (p.sxx + p.syy) + p.szz, dr);
     p.jx = jx;
     p.jy = jy;
     p.jz = jz;
@@ -69,17 +87,17 @@ __device__ __forceinline__ R reconstruct(const Collided<R> &p, int i)
     using L = Lattice<Q>;
     const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
     R lin = p.T;
-    if (cx != 0) lin += (cx > 0 ? R(3) : R(-3)) * p.jx;
-    if (cy != 0) lin += (cy > 0 ? R(3) : R(-3)) * p.jy;
-    if (cz != 0) lin += (cz > 0 ? R(3) : R(-3)) * p.jz;
+    if (cx != 0) lin = fma_(cx > 0 ? R(3) : R(-3), p.jx, lin);
+    if (cy != 0) lin = fma_(cy > 0 ? R(3) : R(-3), p.jy, lin);
+    if (cz != 0) lin = fma_(cz > 0 ? R(3) : R(-3), p.jz, lin);
     R quad = R(0);
     if (cx != 0) quad += p.sxx;
     if (cy != 0) quad += p.syy;
     if (cz != 0) quad += p.szz;
-    if (cx * cy != 0) quad += (cx * cy > 0 ? R(2) : R(-2)) * p.sxy;
-    if (cx * cz != 0) quad += (cx * cz > 0 ? R(2) : R(-2)) * p.sxz;
-    if (cy * cz != 0) quad += (cy * cz > 0 ? R(2) : R(-2)) * p.syz;
-    return R(L::w(i)) * (lin + R(4.5) * quad);
+    if (cx * cy != 0) quad = fma_(cx * cy > 0 ? R(2) : R(-2), p.sxy, quad);
+    if (cx * cz != 0) quad = fma_(cx * cz > 0 ? R(2) : R(-2), p.sxz, quad);
+    if (cy * cz != 0) quad = fma_(cy * cz > 0 ? R(2) : R(-2), p.syz, quad);
+    return R(L::w(i)) * fma_(R(4.5), quad, lin);
 }
 
 // The nine (c_x, c_y) slots of one layer, index (cx+1) + 3 (cy+1).
@@ -117,20 +135,20 @@ __device__ __forceinline__ void reconstruct_layer(const Collided<R> &p, Layer<R>
         Bx = jx3;
         By = jy3;
     } else {
-        A = p.T + R(4.5) * p.szz + R(3 * CZ) * p.jz;
-        Bx = jx3 + R(9 * CZ) * p.sxz;
-        By = jy3 + R(9 * CZ) * p.syz;
+        A = fma_(R(3 * CZ), p.jz, fma_(R(4.5), p.szz, p.T));
+        Bx = fma_(R(9 * CZ), p.sxz, jx3);
+        By = fma_(R(9 * CZ), p.syz, jy3);
     }
-    const R xx = R(4.5) * p.sxx, yy = R(4.5) * p.syy;
-    const R Px = A + xx, Py = A + yy;
+    const R Px = fma_(R(4.5), p.sxx, A), Py = fma_(R(4.5), p.syy, A);
     o.v[4] = R(weight<Q>(0, 0, CZ)) * A;
     o.v[5] = R(weight<Q>(1, 0, CZ)) * (Px + Bx);
     o.v[3] = R(weight<Q>(-1, 0, CZ)) * (Px - Bx);
     o.v[7] = R(weight<Q>(0, 1, CZ)) * (Py + By);
     o.v[1] = R(weight<Q>(0, -1, CZ)) * (Py - By);
     if (has_dir<Q>(1, 1, CZ)) {
-        const R Pxy = Px + yy, s9 = R(9) * p.sxy;
-        const R D1 = Pxy + s9, D2 = Pxy - s9, E1 = Bx + By, E2 = Bx - By;
+        const R Pxy = fma_(R(4.5), p.syy, Px);
+        const R D1 = fma_(R(9), p.sxy, Pxy), D2 = fma_(R(-9), p.sxy, Pxy);
+        const R E1 = Bx + By, E2 = Bx - By;
         o.v[8] = R(weight<Q>(1, 1, CZ)) * (D1 + E1);
         o.v[0] = R(weight<Q>(-1, -1, CZ)) * (D1 - E1);
         o.v[2] = R(weight<Q>(1, -1, CZ)) * (D2 + E2);

@@ -102,7 +102,9 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
     // does not split evenly over the XCDs).
     const int nb = gridDim.x;
     int b = blockIdx.x;
+#ifndef LBM_NO_XCD_REMAP
     if (nb % kXcds == 0) b = (b % kXcds) * (nb / kXcds) + b / kXcds;
+#endif
     const int tx = b % g.tiles_x;
     const int ty = (b / g.tiles_x) % g.tiles_y;
     const int chunk = b / (g.tiles_x * g.tiles_y);
@@ -212,15 +214,15 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
         if (d >= z0 && active) {
             const int64_t o = (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)d * plane;
             const MomentAcc<R> &a = acc[0];
-            const R third = a.r * R(1.0 / 3.0);
+            const R m3 = R(-1.0 / 3.0);
             const R sc = kScaled ? s_pi : R(1);
             store_out(out + o, Store<S>::make(a.r));
             store_out(out + g.N + o, Store<S>::make(a.jx));
             store_out(out + 2 * g.N + o, Store<S>::make(a.jy));
             store_out(out + 3 * g.N + o, Store<S>::make(a.jz));
-            store_out(out + 4 * g.N + o, Store<S>::make(kScaled ? (a.mxx - third) * sc : a.mxx - third));
-            store_out(out + 5 * g.N + o, Store<S>::make(kScaled ? (a.myy - third) * sc : a.myy - third));
-            store_out(out + 6 * g.N + o, Store<S>::make(kScaled ? (a.mzz - third) * sc : a.mzz - third));
+            store_out(out + 4 * g.N + o, Store<S>::make(kScaled ? fma_(m3, a.r, a.mxx) * sc : fma_(m3, a.r, a.mxx)));
+            store_out(out + 5 * g.N + o, Store<S>::make(kScaled ? fma_(m3, a.r, a.myy) * sc : fma_(m3, a.r, a.myy)));
+            store_out(out + 6 * g.N + o, Store<S>::make(kScaled ? fma_(m3, a.r, a.mzz) * sc : fma_(m3, a.r, a.mzz)));
             store_out(out + 7 * g.N + o, Store<S>::make(kScaled ? a.mxy * sc : a.mxy));
             store_out(out + 8 * g.N + o, Store<S>::make(kScaled ? a.mxz * sc : a.mxz));
             store_out(out + 9 * g.N + o, Store<S>::make(kScaled ? a.myz * sc : a.myz));
@@ -241,14 +243,9 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
 // Chunk length along z.  Each chunk re-reads two halo planes that the
 // neighbouring chunk also reads, at another time and usually on another XCD,
 // so the re-read costs HBM bandwidth: chunks are made as long as possible
-// while still giving about one resident round of workgroups (two per CU on
-// 256 CUs).
-#ifndef LBM_TARGET_BLOCKS
-#define LBM_TARGET_BLOCKS 512
-#endif
-inline int choose_zchunk(int nz, int tiles_xy)
+// while still giving about one resident round of workgroups on 256 CUs.
+inline int choose_zchunk(int nz, int tiles_xy, int target_blocks)
 {
-    const int target_blocks = LBM_TARGET_BLOCKS;
     int chunks = (target_blocks + tiles_xy - 1) / tiles_xy;
     if (chunks < 1) chunks = 1;
     int zc = (nz + chunks - 1) / chunks;
@@ -257,7 +254,7 @@ inline int choose_zchunk(int nz, int tiles_xy)
     return zc;
 }
 
-template <int Q, class S, int TX, int TY>
+template <int Q, class S, int TX, int TY, int WG_PER_CU>
 hipError_t run(const lbm_ctx *c, const void *in, void *out)
 {
     using R = typename Store<S>::real;
@@ -268,7 +265,7 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out)
     g.N = c->N;
     g.tiles_x = (c->nx + TX - 1) / TX;
     g.tiles_y = (c->ny + TY - 1) / TY;
-    g.zchunk = choose_zchunk(c->nz, g.tiles_x * g.tiles_y);
+    g.zchunk = choose_zchunk(c->nz, g.tiles_x * g.tiles_y, 256 * WG_PER_CU);
     g.chunks = (c->nz + g.zchunk - 1) / g.zchunk;
     const int64_t blocks = (int64_t)g.tiles_x * g.tiles_y * g.chunks;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
@@ -278,14 +275,17 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out)
     return hipGetLastError();
 }
 
+// Tiles: 64 x 16 nodes (1024 threads, one workgroup per CU, 114 KB of LDS
+// for D3Q27 FP32) for FP32 and 16-bit storage; 32 x 8 (two per CU) for FP64,
+// whose populations take twice the LDS.
 template <int Q>
 hipError_t dispatch_storage(const lbm_ctx *c, const void *in, void *out)
 {
     switch (c->storage) {
-    case LBM_STORE_F64: return run<Q, double, 32, 8>(c, in, out);
-    case LBM_STORE_F32: return run<Q, float, 32, 16>(c, in, out);
-    case LBM_STORE_F16: return run<Q, f16, 32, 16>(c, in, out);
-    case LBM_STORE_BF16: return run<Q, bf16, 32, 16>(c, in, out);
+    case LBM_STORE_F64: return run<Q, double, 32, 8, 2>(c, in, out);
+    case LBM_STORE_F32: return run<Q, float, 64, 16, 1>(c, in, out);
+    case LBM_STORE_F16: return run<Q, f16, 64, 16, 1>(c, in, out);
+    case LBM_STORE_BF16: return run<Q, bf16, 64, 16, 1>(c, in, out);
     default: return hipErrorInvalidValue;
     }
 }

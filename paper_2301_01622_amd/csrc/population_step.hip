@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_population_pull(const S *__restrict__ i
         accumulate<Q, R>(a, f[i], i);
     }
     // Equilibrium (Eq. 5) in shifted form: reconstruction of S = j j / rho.
-    const R inv_rho = R(1) / (R(1) + a.r);
+    const R inv_rho = reciprocal<R>(R(1) + a.r);
     Collided<R> eq;
     eq.jx = a.jx;
     eq.jy = a.jy;
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_population_pull(const S *__restrict__ i
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const R feq = reconstruct<Q, R>(eq, i);
-        out[(int64_t)i * N + n] = Store<S>::make(f[i] + omega * (feq - f[i]));
+        out[(int64_t)i * N + n] = Store<S>::make(fma_(omega, feq - f[i], f[i]));
     }
 }
 
