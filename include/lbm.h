@@ -100,12 +100,18 @@ void lbm_default_opts(lbm_opts *opts);
 
 /* Creates a context: validates the arguments, allocates the two state copies
  * (flip-flop, Sec. III.A) on the device and initialises the fluid at rest
- * (rho = 1, u = 0, P = c_s^2 I; species 1 fills the box).
+ * (rho = 1, u = 0, P = c_s^2 I; with two species, species 2 fills the box).
  *   grid    : box size, every side >= 3
  *   lattice : 19 or 27
  *   tau     : BGK relaxation time (Eq. 7, omega = 1/tau), > 1/2
- *   species : 1, or 2 for the colour-gradient mixture (moment scheme, D3Q19
- *             or D3Q27, FP32/FP64 storage)
+ *   species : 1, or 2 for the colour-gradient mixture (moment scheme only,
+ *             FP32/FP64 storage).  Two species: phase field
+ *             phi = (rho1 - rho2)/rho, colour gradient
+ *             G = (1/c_s^2) sum_i w_i c_i phi(x + c_i), perturbation with second
+ *             moment (A/9)(G G/|G| - |G| I), A = 9 sigma/(2 tau), recolouring
+ *             beta (rho1 rho2/rho) w_i (c_i.n)/|c_i| (operators the paper names
+ *             in Sec. III.A; sigma = 2 A tau / 9 is the surface tension of the
+ *             interfacial force F_surf of Sec. III.B), n = G / max(|G|, 1e-3)
  *   opts    : NULL for the defaults
  * On success *out holds the context; on failure *out is NULL.
  * Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE. */

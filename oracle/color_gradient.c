@@ -11,13 +11,17 @@
  *
  *   phase field     phi = (rho1 - rho2)/(rho1 + rho2)           (Sec. III.B)
  *   colour gradient G = (1/c_s^2) sum_i w_i c_i phi(y + c_i)   (isotropic)
- *   normal          n = G/|G| if |G| > EPS_G, else n = 0 and both operators
- *                   below vanish
- *   perturbation    Df_i = (A/2)|G| [w_i (c_i.n)^2 - B_i], B_0 = w_0 - 2/3,
+ *   normal          n = G / max(|G|, EPS_G), EPS_G = 1e-3: the unit normal
+ *                   wherever |G| >= EPS_G (every real interface), and a
+ *                   continuous fade to zero where the gradient vanishes (at
+ *                   saddle points of phi between two interfaces the unit
+ *                   normal is undefined, so no direction is preferred)
+ *   perturbation    Df_i = (A/2)|G| [w_i (c_i.G)^2/|G|^2 - B_i], B_0 = w_0 - 2/3,
  *                   B_i = w_i otherwise (three-dimensional operator of Liu,
  *                   Valocchi and Kang); it carries no mass and no momentum,
  *                   and its second moment is
- *                   DP_ab = (A/9)|G| (n_a n_b - delta_ab);
+ *                   DP_ab = (A/9) (G_a G_b/|G| - |G| delta_ab), continuous in G
+ *                   (zero at G = 0), so it needs no threshold;
  *                   surface tension sigma = 2 A tau / 9
  *   recolouring     f^k_i = (rho^k/rho) f'_i
  *                           + s_k beta (rho1 rho2/rho) w_i (c_i.n)/|c_i|,
@@ -38,7 +42,7 @@
 
 #include "oracle.h"
 
-#define EPS_G 1e-8
+#define EPS_G 1e-3
 
 /* Two-component SoA layout: rho1, rho2, jx, jy, jz, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz. */
 static void load_node2(const double *H, long N, long n, double *rho1, double *rho2, double j[3],
@@ -66,8 +70,8 @@ static void store_node2(double *H, long N, long n, double rho1, double rho2, con
     H[10 * N + n] = P[1][2];
 }
 
-/* Colour gradient G at node (x,y,z) from the phase field, its norm, and the
- * unit normal (zero below the threshold). */
+/* Colour gradient G at node (x,y,z) from the phase field, its norm |G|, and
+ * the recolouring direction n = G / max(|G|, EPS_G). */
 static void colour_gradient(const ora_lat *L, const double *phi, int nx, int ny, int nz, int x, int y,
                             int z, double G[3], double *Gnorm, double nrm[3])
 {
@@ -77,8 +81,8 @@ static void colour_gradient(const ora_lat *L, const double *phi, int nx, int ny,
         for (int a = 0; a < 3; ++a) G[a] += L->w[i] * L->c[i][a] * phi[nb] / ORA_CS2;
     }
     *Gnorm = sqrt(G[0] * G[0] + G[1] * G[1] + G[2] * G[2]);
-    for (int a = 0; a < 3; ++a) nrm[a] = *Gnorm > EPS_G ? G[a] / *Gnorm : 0.0;
-    if (!(*Gnorm > EPS_G)) *Gnorm = 0.0;
+    double d = *Gnorm > EPS_G ? *Gnorm : EPS_G;
+    for (int a = 0; a < 3; ++a) nrm[a] = G[a] / d;
 }
 
 static double speed(const ora_lat *L, int i)
@@ -120,7 +124,7 @@ static void cg_moment_step(const ora_lat *L, int nx, int ny, int nz, double omeg
                 ora_hermite_parts(L, rho, j, P, heq, hneq);
                 for (int a = 0; a < 3; ++a)
                     for (int b = 0; b < 3; ++b)
-                        DP[a][b] = A / 9.0 * Gnorm * (nrm[a] * nrm[b] - (a == b ? 1.0 : 0.0));
+                        DP[a][b] = Gnorm > 0.0 ? A / 9.0 * (G[a] * G[b] / Gnorm - (a == b ? Gnorm : 0.0)) : 0.0;
                 for (int i = 0; i < q; ++i) {
                     /* Eq. 7, then the reconstructed perturbation w_i Q_i:DP. */
                     double hpost = (1.0 - omega) * (heq[i] + hneq[i]) + omega * heq[i];
@@ -217,9 +221,9 @@ static void cg_population_step(const ora_lat *L, int nx, int ny, int nz, double 
 
                 /* Perturbation operator, written per population. */
                 for (int i = 0; i < q; ++i) {
-                    double cn = L->c[i][0] * nrm[0] + L->c[i][1] * nrm[1] + L->c[i][2] * nrm[2];
+                    double cG = L->c[i][0] * G[0] + L->c[i][1] * G[1] + L->c[i][2] * G[2];
                     double B = i == 0 ? L->w[0] - 2.0 / 3.0 : L->w[i];
-                    Df[i] = Gnorm > 0.0 ? A / 2.0 * Gnorm * (L->w[i] * cn * cn - B) : 0.0;
+                    Df[i] = Gnorm > 0.0 ? A / 2.0 * Gnorm * (L->w[i] * cG * cG / (Gnorm * Gnorm) - B) : 0.0;
                 }
                 if (regularize) {
                     /* Keep only the Hermite (second-order) part of Df. */

@@ -138,7 +138,6 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     if (species == 2 && (!(o.beta >= 0.0) || !(o.sigma >= 0.0))) return LBM_EINVAL;
     if (!(o.s_pi >= 0.0) || !std::isfinite(o.s_pi)) return LBM_EINVAL;
     if (species == 2 && o.scheme == LBM_SCHEME_POPULATION) return LBM_EINVAL;
-    if (species == 2) return LBM_EINVAL;  // two-species kernels are not built yet
 
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
     if (!c) return LBM_ENOMEM;
@@ -181,8 +180,8 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
         lbm_destroy(c);
         return LBM_ENOMEM;
     }
-    // Fluid at rest: every stored deviation is zero (species 1 fills the box,
-    // so rho1 = 1 for two species).
+    // Fluid at rest: every stored deviation is zero (for two species rho1 = 0:
+    // species 2 fills the box).
     for (int k = 0; k < 2; ++k) {
         if (hipMemsetAsync(c->state[k], 0, bytes, c->stream) != hipSuccess) {
             lbm_destroy(c);
@@ -311,8 +310,9 @@ int lbm_step(lbm_ctx *c, int n)
     for (int t = 0; t < n; ++t) {
         const void *in = c->state[c->cur];
         void *out = c->state[1 - c->cur];
-        hipError_t e = c->scheme == LBM_SCHEME_MOMENT ? lbm::launch_moment_step(c, in, out)
-                                                      : lbm::launch_population_step(c, in, out);
+        hipError_t e = c->scheme == LBM_SCHEME_POPULATION ? lbm::launch_population_step(c, in, out)
+                       : c->species == 2                  ? lbm::launch_cg_step(c, in, out)
+                                                          : lbm::launch_moment_step(c, in, out);
         if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
         c->cur = 1 - c->cur;
         ++c->steps;

@@ -33,6 +33,9 @@ constexpr int kReduceBlocks = 1024;
 // Moment scheme.
 hipError_t launch_moment_step(const lbm_ctx *c, const void *in, void *out);
 
+// Moment scheme, two species (colour gradient).
+hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out);
+
 // Population scheme.
 hipError_t launch_population_step(const lbm_ctx *c, const void *in, void *out);
 

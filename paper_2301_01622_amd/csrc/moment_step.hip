@@ -29,60 +29,10 @@
 #include "internal.hpp"
 #include "moment_math.hpp"
 #include "storage.hpp"
+#include "tile_common.hpp"
 
 namespace lbm {
 namespace {
-
-constexpr int kXcds = 8;
-
-struct TileGrid {
-    int nx, ny, nz;
-    int64_t N;
-    int tiles_x, tiles_y, chunks, zchunk;
-};
-
-// Moments of one source node, already unpacked to the arithmetic type.
-template <class R>
-struct Moments {
-    R v[10];
-};
-
-template <class S>
-__device__ __forceinline__ void load_moments(const S *__restrict__ in, int64_t N, int64_t idx,
-                                             Moments<typename Store<S>::real> &m)
-{
-#pragma unroll
-    for (int k = 0; k < 10; ++k) m.v[k] = Store<S>::load(in[k * N + idx]);
-}
-
-template <class S>
-__device__ __forceinline__ void store_out(S *p, S v)
-{
-    __builtin_nontemporal_store(v, p);
-}
-template <>
-__device__ __forceinline__ void store_out<bf16>(bf16 *p, bf16 v)
-{
-    __builtin_nontemporal_store(v.bits, reinterpret_cast<uint16_t *>(p));
-}
-
-// LDS slot of direction (slot, layer CZ), slot = (cx+1) + 3 (cy+1); the
-// own-column slot 4 never goes through LDS.  Directions absent from the
-// lattice get no slot.  Returns -1 for "no slot".
-template <int Q>
-__host__ __device__ constexpr int lds_slot(int cz, int slot)
-{
-    int k = 0;
-    for (int z = -1; z <= 1; ++z)
-        for (int sl = 0; sl < 9; ++sl) {
-            if (sl == 4 || !has_dir<Q>(sl % 3 - 1, sl / 3 - 1, z)) continue;
-            if (z == cz && sl == slot) return k;
-            ++k;
-        }
-    return -1;
-}
-template <int Q>
-constexpr int kLdsSlots = Q - 3;
 
 template <int Q, class S, int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in, S *__restrict__ out, TileGrid g,
@@ -98,13 +48,7 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
     static_assert(RING <= NT, "halo ring must fit one pass");
     __shared__ R lds[kLdsSlots<Q> * HN];
 
-    // XCD-aware tile numbering (falls back to the identity when the grid
-    // does not split evenly over the XCDs).
-    const int nb = gridDim.x;
-    int b = blockIdx.x;
-#ifndef LBM_NO_XCD_REMAP
-    if (nb % kXcds == 0) b = (b % kXcds) * (nb / kXcds) + b / kXcds;
-#endif
+    const int b = xcd_tile_id();
     const int tx = b % g.tiles_x;
     const int ty = (b / g.tiles_x) % g.tiles_y;
     const int chunk = b / (g.tiles_x * g.tiles_y);
@@ -133,10 +77,7 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
     }
     auto wrap_xy = [&](int h) -> int64_t {
         const int hx = h % HX, hy = h / HX;
-        int gx = (x0 - 1 + hx) % g.nx, gy = (y0 - 1 + hy) % g.ny;
-        gx += gx < 0 ? g.nx : 0;
-        gy += gy < 0 ? g.ny : 0;
-        return (int64_t)gx + (int64_t)g.nx * gy;
+        return (int64_t)wrap_coord(x0 - 1 + hx, g.nx) + (int64_t)g.nx * wrap_coord(y0 - 1 + hy, g.ny);
     };
     const int64_t own_xy = wrap_xy(h0);
     const int64_t ring_xy = has_ring ? wrap_xy(hr) : 0;
@@ -238,20 +179,6 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
         plane_step(p, own_a, ring_a);
         if (p + 1 <= z_end) plane_step(p + 1, own_b, ring_b);
     }
-}
-
-// Chunk length along z.  Each chunk re-reads two halo planes that the
-// neighbouring chunk also reads, at another time and usually on another XCD,
-// so the re-read costs HBM bandwidth: chunks are made as long as possible
-// while still giving about one resident round of workgroups on 256 CUs.
-inline int choose_zchunk(int nz, int tiles_xy, int target_blocks)
-{
-    int chunks = (target_blocks + tiles_xy - 1) / tiles_xy;
-    if (chunks < 1) chunks = 1;
-    int zc = (nz + chunks - 1) / chunks;
-    if (zc < 16) zc = 16;
-    if (zc > nz) zc = nz;
-    return zc;
 }
 
 template <int Q, class S, int TX, int TY, int WG_PER_CU>

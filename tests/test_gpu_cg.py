@@ -1,0 +1,162 @@
+"""GPU parity of the two-component (colour-gradient) step against the FP64
+oracle.  Same conventions as test_gpu_parity.py: both sides start from the
+same seeded fields and build their states with their own code."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2301_01622_amd import inputs as I  # noqa: E402
+
+TAU, SIGMA, BETA = 0.8, 0.01, 0.7
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def LBM():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2301_01622_amd.lbm import LBM as _LBM
+    return _LBM
+
+
+def _state(oracle, shape, seed, neq=0.0):
+    nz, ny, nx = shape
+    r1, r2, u = I.droplets(shape, centres=[(nx * 0.3, ny * 0.45, nz * 0.5), (nx * 0.7, ny * 0.55, nz * 0.5)],
+                           radius=min(shape) * 0.25, velocities=[(0.05, 0.0, 0.0), (-0.05, 0.0, 0.0)])
+    H = oracle.equilibrium_moments2(r1, r2, u)
+    if neq:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        H[5:] += neq * rng.standard_normal(H[5:].shape)
+    return np.ascontiguousarray(H)
+
+
+def _gpu(LBM, H, q, steps, storage, tau=TAU):
+    nf, nz, ny, nx = H.shape
+    sim = LBM((nx, ny, nz), q, tau, species=2, storage=storage, sigma=SIGMA, beta=BETA)
+    sim.set_moments(torch.from_numpy(H).cuda())
+    sim.step(steps)
+    out = sim.get_moments(torch.float64).cpu().numpy()
+    sim.close()
+    return out
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_ragged_droplets(LBM, oracle, q, storage, tol):
+    shape = (23, 29, 37)
+    _say(f"two-component ragged {shape} D3Q{q} {storage} 12 steps")
+    H = _state(oracle, shape, seed=5, neq=1e-3)
+    ref = oracle.cg_moment_run(H, q, TAU, oracle.sigma_to_A(SIGMA, TAU), BETA, 12)
+    got = _gpu(LBM, H, q, 12, storage)
+    err = np.abs(got - ref).max(axis=(1, 2, 3))
+    _say(f"  max err per field {err}")
+    assert err.max() <= tol
+
+
+def test_flat_regions_and_minimum_box(LBM, oracle):
+    """3^3 box, one species nearly everywhere: gradients vanish below the
+    threshold in most nodes (the normal is switched off there)."""
+    H = _state(oracle, (3, 3, 3), seed=1)
+    ref = oracle.cg_moment_run(H, 19, TAU, oracle.sigma_to_A(SIGMA, TAU), BETA, 4)
+    got = _gpu(LBM, H, 19, 4, "f64")
+    assert np.abs(got - ref).max() <= 1e-12
+
+
+def _sampled(oracle, H0, q, steps, nodes):
+    r = 2 * steps  # the colour gradient reaches two nodes per step
+    out = []
+    A = oracle.sigma_to_A(SIGMA, TAU)
+    for (z, y, x) in nodes:
+        idx = [np.arange(c - r, c + r + 1) for c in (z, y, x)]
+        blk = H0.take(idx[0], axis=1, mode="wrap").take(idx[1], axis=2, mode="wrap").take(idx[2], axis=3, mode="wrap")
+        out.append(oracle.cg_moment_run(np.ascontiguousarray(blk), q, TAU, A, BETA, steps)[:, r, r, r])
+    return np.array(out)
+
+
+@pytest.mark.parametrize("steps", [1, 2])
+def test_full_size_droplet_collision_sampled(LBM, oracle, steps):
+    """512 x 256 x 256 droplet collision (R = 40, u = +-0.05), D3Q19 FP32, in
+    the launch configuration of the benchmark: nodes on the interfaces, in
+    the drops, in the carrier and on the box faces, node by node."""
+    shape = (256, 256, 512)
+    _say(f"512x256x256 two-component sampled, {steps} steps")
+    r1, r2, u = I.droplet_collision_512(shape)
+    H0 = oracle.equilibrium_moments2(r1, r2, u)
+    sim = LBM((512, 256, 256), 19, TAU, species=2, storage="f32", sigma=SIGMA, beta=BETA)
+    sim.set_equilibrium(torch.from_numpy(np.stack([r1, r2])).cuda(), torch.from_numpy(u).cuda())
+    sim.step(steps)
+    got = sim.get_moments(torch.float64).cpu().numpy()
+    sim.close()
+    rng = np.random.default_rng(3)
+    nodes = [(0, 0, 0), (255, 255, 511), (128, 118, 136), (128, 118, 216), (128, 158, 336), (128, 128, 256)]
+    # random nodes near the two interfaces
+    for _ in range(24):
+        c = [(128, 118, 176), (128, 138, 336)][rng.integers(2)]
+        d = rng.standard_normal(3)
+        d *= 40.0 / np.linalg.norm(d)
+        nodes.append(tuple(int(round(c[k] + d[k])) % shape[k] for k in range(3)))
+    nodes += [tuple(int(v) for v in (rng.integers(0, 256), rng.integers(0, 256), rng.integers(0, 512)))
+              for _ in range(10)]
+    ref = _sampled(oracle, H0, 19, steps, nodes)
+    g = np.array([got[:, z, y, x] for (z, y, x) in nodes])
+    err = np.abs(g - ref).max(axis=0)
+    _say(f"  max err per field {err}")
+    assert err.max() <= 1e-6
+
+
+def test_full_size_conservation(LBM):
+    shape = (256, 256, 512)
+    _say("512x256x256 two-component conservation, 100 steps")
+    r1, r2, u = I.droplet_collision_512(shape)
+    sim = LBM((512, 256, 256), 19, TAU, species=2, storage="f32", sigma=SIGMA, beta=BETA)
+    sim.set_equilibrium(torch.from_numpy(np.stack([r1, r2])).cuda(), torch.from_numpy(u).cuda())
+    t0 = sim.reduce()
+    sim.step(100)
+    t1 = sim.reduce()
+    sim.close()
+    _say(f"  totals before {t0} after {t1}")
+    n = 512 * 256 * 256
+    # FP32 rounding of O(1) species populations (rho1 stored directly) and of
+    # the shifted mixture populations, as a random walk over N x T updates.
+    bound_species = 8 * 2.0 ** -24 * 1.0 * np.sqrt(n * 100)
+    bound_j = 8 * 2.0 ** -24 * 0.15 * np.sqrt(n * 100)
+    assert abs(t1[0] - t0[0]) <= bound_species
+    assert abs(t1[1] - t0[1]) <= bound_species
+    assert np.abs(t1[2:] - t0[2:]).max() <= bound_j
+
+
+def test_droplet_collision_run(LBM, oracle):
+    """Head-off-axis droplet collision at reduced size (48^3, R = 8, D3Q19,
+    FP32) for 300 steps: velocities within 1e-4, densities within 1e-3 of the
+    FP64 oracle, and the drop-averaged density <rho>_{rho > 0.5} within 1e-4."""
+    shape = (48, 48, 48)
+    _say("droplet collision 48^3 D3Q19 f32 300 steps")
+    r1, r2, u = I.droplets(shape, centres=[(14.0, 21.0, 24.0), (34.0, 25.0, 24.0)], radius=8.0,
+                           velocities=[(0.05, 0.0, 0.0), (-0.05, 0.0, 0.0)])
+    H0 = oracle.equilibrium_moments2(r1, r2, u)
+    ref = oracle.cg_moment_run(H0, 19, TAU, oracle.sigma_to_A(SIGMA, TAU), BETA, 300)
+    got = _gpu(LBM, H0, 19, 300, "f32")
+    vg = got[2:5] / (got[0] + got[1])
+    vr = ref[2:5] / (ref[0] + ref[1])
+    du = np.abs(vg - vr).max()
+    drho = np.abs(got[:2] - ref[:2]).max()
+    mg = got[0][got[0] > 0.5].mean()
+    mr = ref[0][ref[0] > 0.5].mean()
+    _say(f"  max|du|={du:.3e} max|drho^k|={drho:.3e} <rho1>_(>0.5) gpu {mg:.8f} oracle {mr:.8f}")
+    assert du <= 1e-4 and drho <= 1e-3 and abs(mg / mr - 1) <= 1e-4
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_translation_bitwise_two_component(LBM, oracle, storage):
+    shape = (21, 19, 45)
+    H = _state(oracle, shape, seed=9, neq=1e-3)
+    shift = (5, 3, 11)
+    Hs = np.ascontiguousarray(np.roll(H, shift, axis=(1, 2, 3)))
+    a = _gpu(LBM, H, 19, 5, storage)
+    b = _gpu(LBM, Hs, 19, 5, storage)
+    np.testing.assert_array_equal(np.roll(a, shift, axis=(1, 2, 3)), b)
