@@ -77,6 +77,36 @@ def cpu_baseline(n: int, q: int, tau: float, steps: int, rho, u):
     }
 
 
+def two_component(steps: int, warmup: int):
+    """512 x 256 x 256 two-component droplet collision (D3Q19, FP32, tau = 0.8,
+    sigma = 0.01, beta = 0.7): drops of radius 40 at +-0.05 along x."""
+    import numpy as np
+    import torch
+    from paper_2301_01622_amd import inputs
+    from paper_2301_01622_amd.lbm import LBM
+
+    shape = (256, 256, 512)
+    r1, r2, u = inputs.droplet_collision_512(shape)
+    stream = torch.cuda.Stream()
+    N = 512 * 256 * 256
+    with torch.cuda.stream(stream):
+        sim = LBM((512, 256, 256), 19, 0.8, species=2, storage="f32", sigma=0.01, beta=0.7, stream=stream)
+        sim.set_equilibrium(torch.from_numpy(np.stack([r1, r2])).cuda(), torch.from_numpy(u).cuda())
+        ms = time_steps(sim, stream, steps, warmup)
+        state_bytes, step_bytes = sim.memory_info()
+        sim.close()
+    return {
+        "workload": "512x256x256 two-component droplet collision, D3Q19, FP32 (rho-1, rho1, j, P), tau=0.8, "
+                    "sigma=0.01, beta=0.7, R=40, u=+-0.05",
+        "value": round(N / (ms * 1e-3) / 1e6, 1),
+        "unit": "MLUPS",
+        "steps": steps,
+        "ms_per_step": round(ms, 5),
+        "hbm_frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "bytes_per_node_state": state_bytes // N,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +116,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-population", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-two-component", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=10,
                     help="also time this many state copies (plain copy kernel of known size)")
     args = ap.parse_args()
@@ -142,6 +173,10 @@ def main() -> int:
                 "bytes_per_node_state": p_state // N,
             }
 
+    two = None
+    if not args.no_two_component:
+        two = two_component(args.steps // 4 or 1, args.warmup)
+
     mlups = N / (ms * 1e-3) / 1e6
     achieved = step_bytes / (ms * 1e-3) / 1e9
     traffic = measured_traffic(N)
@@ -177,6 +212,8 @@ def main() -> int:
         "copy_kernel": copy,
         "population_lb": pop,
     }
+    if two:
+        line["two_component"] = two
     if copy:
         line["roofline"]["frac_of_measured_copy"] = round(achieved / copy["gbs"], 4)
     if pop:

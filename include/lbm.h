@@ -108,10 +108,11 @@ void lbm_default_opts(lbm_opts *opts);
  *             FP32/FP64 storage).  Two species: phase field
  *             phi = (rho1 - rho2)/rho, colour gradient
  *             G = (1/c_s^2) sum_i w_i c_i phi(x + c_i), perturbation with second
- *             moment (A/9)(G G/|G| - |G| I), A = 9 sigma/(2 tau), recolouring
+ *             moment (A/9)(G G - |G|^2 I)/D, A = 9 sigma/(2 tau), recolouring
  *             beta (rho1 rho2/rho) w_i (c_i.n)/|c_i| (operators the paper names
  *             in Sec. III.A; sigma = 2 A tau / 9 is the surface tension of the
- *             interfacial force F_surf of Sec. III.B), n = G / max(|G|, 1e-3)
+ *             interfacial force F_surf of Sec. III.B), n = G/D, with the
+ *             smoothed norm D = sqrt(|G|^2 + 1e-6)
  *   opts    : NULL for the defaults
  * On success *out holds the context; on failure *out is NULL.
  * Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE. */
@@ -168,6 +169,30 @@ int lbm_state_bytes(const lbm_ctx *ctx, int64_t *bytes);
  * bit like the saved one.  Errors: LBM_EINVAL (NULL), LBM_EDEVICE. */
 int lbm_save_state(lbm_ctx *ctx, void *dst_device);
 int lbm_load_state(lbm_ctx *ctx, const void *src_device);
+
+/* One time step from a saved state to another buffer, both in the format of
+ * lbm_save_state (device, lbm_state_bytes() bytes each, must not overlap);
+ * the context's own state is not touched.  Used to recompute the states of
+ * a checkpointed segment straight into the adjoint's buffers.
+ * Errors: LBM_EINVAL, LBM_ESTATE (population scheme), LBM_EDEVICE. */
+int lbm_step_state(lbm_ctx *ctx, const void *src_state, void *dst_state);
+
+/* One reverse step of the discrete adjoint of the one-species moment scheme
+ * (the exact transpose of the Jacobian of one step, Eqs. 4-9 and 1-3).
+ *   state_t    : device, the state M(t) the forward step started from, in the
+ *                format of lbm_save_state
+ *   lam_next   : device, co-state of M(t+1) in the public layout (10 fields of
+ *                N values: rho, j, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz), FP64 for
+ *                LBM_STORE_F64 contexts, FP32 otherwise
+ *   lam_out    : device, receives the co-state of M(t), same layout; must not
+ *                overlap lam_next
+ *   dtau_accum : device pointer to one double or NULL; the step adds its
+ *                contribution to dL/dtau (sum over nodes, FP64, fixed order)
+ * A stored off-diagonal P component stands for P_ab and P_ba together, so
+ * its co-state is the derivative with respect to that one stored value.
+ * Asynchronous.  Errors: LBM_EINVAL (NULL), LBM_ESTATE (two species or the
+ * population scheme), LBM_EDEVICE. */
+int lbm_adjoint_step(lbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out, double *dtau_accum);
 
 /* Number of time steps advanced since creation or the last set_* call. */
 int64_t lbm_steps_done(const lbm_ctx *ctx);

@@ -47,6 +47,8 @@ def _load():
             "ora_population_run": (i, [i, i, i, i, d, i, i, dp]),
             "ora_cg_moment_run": (i, [i, i, i, i, d, d, d, i, dp]),
             "ora_cg_population_run": (i, [i, i, i, i, d, d, d, i, i, dp, dp]),
+            "ora_moment_adjoint_step": (i, [i, i, i, i, d, dp, dp, dp, dp]),
+            "ora_cg_adjoint_step": (i, [i, i, i, i, d, d, d, dp, dp, dp, dp]),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(lib, name)
@@ -199,3 +201,61 @@ def cg_moments_from_populations(f1, f2, q: int) -> np.ndarray:
     """Two-component moments (rho1, rho2, j, P) of species populations."""
     Ht = moments_from_populations(np.ascontiguousarray(f1 + f2), q)
     return np.ascontiguousarray(np.concatenate([f1.sum(0)[None], f2.sum(0)[None], Ht[1:]], axis=0))
+
+
+# ---- discrete adjoint ---------------------------------------------------------------
+
+def moment_adjoint_step(M, lam_next, q: int, tau: float):
+    """Transposed Jacobian of one single-component step at state M applied to
+    lam_next; returns (lam, dL/domega contribution of this step)."""
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    lam_next = np.ascontiguousarray(lam_next, dtype=np.float64)
+    assert M.shape == lam_next.shape and M.shape[0] == 10
+    _, nz, ny, nx = M.shape
+    lam = np.zeros_like(M)
+    dom = ctypes.c_double(0.0)
+    _check(_load().ora_moment_adjoint_step(q, nx, ny, nz, tau, _dp(M), _dp(lam_next), _dp(lam),
+                                           ctypes.byref(dom)), "moment_adjoint_step")
+    return lam, dom.value
+
+
+def moment_rollout_gradient(M0, lam_T, q: int, tau: float, nsteps: int):
+    """Gradient of a scalar loss L(M(T)) with respect to M(0) and tau, given
+    lam_T = dL/dM(T): forward states kept in memory, then nsteps adjoint steps."""
+    states = [np.ascontiguousarray(M0, dtype=np.float64)]
+    for _ in range(nsteps - 1):
+        states.append(moment_run(states[-1], q, tau, 1))
+    lam = np.ascontiguousarray(lam_T, dtype=np.float64)
+    dL_domega = 0.0
+    for t in reversed(range(nsteps)):
+        lam, dom = moment_adjoint_step(states[t], lam, q, tau)
+        dL_domega += dom
+    return lam, -dL_domega / (tau * tau)
+
+
+def cg_adjoint_step(M, lam_next, q: int, tau: float, sigma: float, beta: float):
+    """Transposed Jacobian of one two-component step (fixed sigma); returns
+    (lam, dL/dtau contribution of this step)."""
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    lam_next = np.ascontiguousarray(lam_next, dtype=np.float64)
+    assert M.shape == lam_next.shape and M.shape[0] == 11
+    _, nz, ny, nx = M.shape
+    lam = np.zeros_like(M)
+    dt = ctypes.c_double(0.0)
+    _check(_load().ora_cg_adjoint_step(q, nx, ny, nz, tau, sigma_to_A(sigma, tau), beta, _dp(M), _dp(lam_next),
+                                       _dp(lam), ctypes.byref(dt)), "cg_adjoint_step")
+    return lam, dt.value
+
+
+def cg_rollout_gradient(M0, lam_T, q: int, tau: float, sigma: float, beta: float, nsteps: int):
+    """Gradient of L(M(T)) w.r.t. the two-component M(0) and tau (fixed sigma)."""
+    A = sigma_to_A(sigma, tau)
+    states = [np.ascontiguousarray(M0, dtype=np.float64)]
+    for _ in range(nsteps - 1):
+        states.append(cg_moment_run(states[-1], q, tau, A, beta, 1))
+    lam = np.ascontiguousarray(lam_T, dtype=np.float64)
+    dL_dtau = 0.0
+    for t in reversed(range(nsteps)):
+        lam, dt = cg_adjoint_step(states[t], lam, q, tau, sigma, beta)
+        dL_dtau += dt
+    return lam, dL_dtau

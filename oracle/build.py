@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["lattice.c", "moment_lb.c", "population_lb.c", "color_gradient.c", "adjoint.c"]
+SOURCES = ["lattice.c", "moment_lb.c", "population_lb.c", "color_gradient.c", "adjoint.c", "adjoint_cg.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -11,17 +11,17 @@
  *
  *   phase field     phi = (rho1 - rho2)/(rho1 + rho2)           (Sec. III.B)
  *   colour gradient G = (1/c_s^2) sum_i w_i c_i phi(y + c_i)   (isotropic)
- *   normal          n = G / max(|G|, EPS_G), EPS_G = 1e-3: the unit normal
- *                   wherever |G| >= EPS_G (every real interface), and a
- *                   continuous fade to zero where the gradient vanishes (at
+ *   smoothed norm   D = sqrt(|G|^2 + EPS_G^2), EPS_G = 1e-3
+ *   normal          n = G / D: the unit normal on every interface (|G| ~ 0.1-0.5
+ *                   there, relative deviation EPS_G^2/(2|G|^2) < 1e-4), and a
+ *                   smooth fade to zero where the gradient vanishes (at
  *                   saddle points of phi between two interfaces the unit
  *                   normal is undefined, so no direction is preferred)
- *   perturbation    Df_i = (A/2)|G| [w_i (c_i.G)^2/|G|^2 - B_i], B_0 = w_0 - 2/3,
+ *   perturbation    Df_i = (A/2) [w_i (c_i.G)^2 - B_i |G|^2] / D, B_0 = w_0 - 2/3,
  *                   B_i = w_i otherwise (three-dimensional operator of Liu,
- *                   Valocchi and Kang); it carries no mass and no momentum,
- *                   and its second moment is
- *                   DP_ab = (A/9) (G_a G_b/|G| - |G| delta_ab), continuous in G
- *                   (zero at G = 0), so it needs no threshold;
+ *                   Valocchi and Kang, written with G instead of |G| n); it
+ *                   carries no mass and no momentum, and its second moment is
+ *                   DP_ab = (A/9) (G_a G_b - |G|^2 delta_ab) / D, smooth in G;
  *                   surface tension sigma = 2 A tau / 9
  *   recolouring     f^k_i = (rho^k/rho) f'_i
  *                           + s_k beta (rho1 rho2/rho) w_i (c_i.n)/|c_i|,
@@ -70,19 +70,18 @@ static void store_node2(double *H, long N, long n, double rho1, double rho2, con
     H[10 * N + n] = P[1][2];
 }
 
-/* Colour gradient G at node (x,y,z) from the phase field, its norm |G|, and
- * the recolouring direction n = G / max(|G|, EPS_G). */
+/* Colour gradient G at node (x,y,z) from the phase field, the smoothed norm
+ * D = sqrt(|G|^2 + EPS_G^2), and the recolouring direction n = G / D. */
 static void colour_gradient(const ora_lat *L, const double *phi, int nx, int ny, int nz, int x, int y,
-                            int z, double G[3], double *Gnorm, double nrm[3])
+                            int z, double G[3], double *D, double nrm[3])
 {
     for (int a = 0; a < 3; ++a) G[a] = 0.0;
     for (int i = 0; i < L->q; ++i) {
         long nb = ora_neighbour(nx, ny, nz, x, y, z, L->c[i][0], L->c[i][1], L->c[i][2]);
         for (int a = 0; a < 3; ++a) G[a] += L->w[i] * L->c[i][a] * phi[nb] / ORA_CS2;
     }
-    *Gnorm = sqrt(G[0] * G[0] + G[1] * G[1] + G[2] * G[2]);
-    double d = *Gnorm > EPS_G ? *Gnorm : EPS_G;
-    for (int a = 0; a < 3; ++a) nrm[a] = G[a] / d;
+    *D = sqrt(G[0] * G[0] + G[1] * G[1] + G[2] * G[2] + EPS_G * EPS_G);
+    for (int a = 0; a < 3; ++a) nrm[a] = G[a] / *D;
 }
 
 static double speed(const ora_lat *L, int i)
@@ -116,15 +115,15 @@ static void cg_moment_step(const ora_lat *L, int nx, int ny, int nz, double omeg
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 long n = (long)x + (long)nx * ((long)y + (long)ny * z);
-                double rho1, rho2, j[3], P[3][3], G[3], Gnorm, nrm[3];
+                double rho1, rho2, j[3], P[3][3], G[3], D, nrm[3];
                 double heq[ORA_QMAX], hneq[ORA_QMAX], DP[3][3];
                 load_node2(Hin, N, n, &rho1, &rho2, j, P);
                 double rho = rho1 + rho2;
-                colour_gradient(L, phi, nx, ny, nz, x, y, z, G, &Gnorm, nrm);
+                colour_gradient(L, phi, nx, ny, nz, x, y, z, G, &D, nrm);
                 ora_hermite_parts(L, rho, j, P, heq, hneq);
+                double G2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
                 for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b)
-                        DP[a][b] = Gnorm > 0.0 ? A / 9.0 * (G[a] * G[b] / Gnorm - (a == b ? Gnorm : 0.0)) : 0.0;
+                    for (int b = 0; b < 3; ++b) DP[a][b] = A / 9.0 * (G[a] * G[b] - (a == b ? G2 : 0.0)) / D;
                 for (int i = 0; i < q; ++i) {
                     /* Eq. 7, then the reconstructed perturbation w_i Q_i:DP. */
                     double hpost = (1.0 - omega) * (heq[i] + hneq[i]) + omega * heq[i];
@@ -209,7 +208,7 @@ static void cg_population_step(const ora_lat *L, int nx, int ny, int nz, double 
             for (int x = 0; x < nx; ++x) {
                 long n = (long)x + (long)nx * ((long)y + (long)ny * z);
                 double f[ORA_QMAX], rho1 = 0.0, rho2 = 0.0, rho, j[3], P[3][3];
-                double heq[ORA_QMAX], hneq[ORA_QMAX], Df[ORA_QMAX], G[3], Gnorm, nrm[3];
+                double heq[ORA_QMAX], hneq[ORA_QMAX], Df[ORA_QMAX], G[3], D, nrm[3];
                 for (int i = 0; i < q; ++i) {
                     rho1 += f1in[(long)i * N + n];
                     rho2 += f2in[(long)i * N + n];
@@ -217,13 +216,14 @@ static void cg_population_step(const ora_lat *L, int nx, int ny, int nz, double 
                 }
                 ora_project(L, f, &rho, j, P);
                 ora_hermite_parts(L, rho, j, P, heq, hneq);
-                colour_gradient(L, phi, nx, ny, nz, x, y, z, G, &Gnorm, nrm);
+                colour_gradient(L, phi, nx, ny, nz, x, y, z, G, &D, nrm);
 
                 /* Perturbation operator, written per population. */
+                double G2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
                 for (int i = 0; i < q; ++i) {
                     double cG = L->c[i][0] * G[0] + L->c[i][1] * G[1] + L->c[i][2] * G[2];
                     double B = i == 0 ? L->w[0] - 2.0 / 3.0 : L->w[i];
-                    Df[i] = Gnorm > 0.0 ? A / 2.0 * Gnorm * (L->w[i] * cG * cG / (Gnorm * Gnorm) - B) : 0.0;
+                    Df[i] = A / 2.0 * (L->w[i] * cG * cG - B * G2) / D;
                 }
                 if (regularize) {
                     /* Keep only the Hermite (second-order) part of Df. */

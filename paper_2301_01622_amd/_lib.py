@@ -83,6 +83,8 @@ def load() -> ctypes.CDLL:
         "lbm_state_bytes": (c_int, [c_void, P(ctypes.c_int64)]),
         "lbm_save_state": (c_int, [c_void, c_void]),
         "lbm_load_state": (c_int, [c_void, c_void]),
+        "lbm_step_state": (c_int, [c_void, c_void, c_void]),
+        "lbm_adjoint_step": (c_int, [c_void, c_void, c_void, c_void, c_void]),
         "lbm_steps_done": (ctypes.c_int64, [c_void]),
         "lbm_strerror": (ctypes.c_char_p, [c_int]),
         "lbm_last_error": (ctypes.c_char_p, [c_void]),

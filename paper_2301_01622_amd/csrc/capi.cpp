@@ -363,6 +363,32 @@ int lbm_load_state(lbm_ctx *c, const void *src)
     return LBM_OK;
 }
 
+int lbm_step_state(lbm_ctx *c, const void *src, void *dst)
+{
+    if (!c) return LBM_EINVAL;
+    if (!src || !dst || src == dst) return fail(c, LBM_EINVAL, "step_state: NULL or identical buffers");
+    if (c->scheme != LBM_SCHEME_MOMENT) return fail(c, LBM_ESTATE, "step_state: moment scheme only");
+    c->err.clear();
+    DeviceGuard g(c->device);
+    hipError_t e = c->species == 2 ? lbm::launch_cg_step(c, src, dst) : lbm::launch_moment_step(c, src, dst);
+    if (e != hipSuccess) return hip_fail(c, e, "step_state");
+    return LBM_OK;
+}
+
+int lbm_adjoint_step(lbm_ctx *c, const void *state, const void *lam_next, void *lam_out, double *dtau_accum)
+{
+    if (!c) return LBM_EINVAL;
+    if (!state || !lam_next || !lam_out || lam_next == lam_out)
+        return fail(c, LBM_EINVAL, "adjoint_step: NULL or aliased buffers");
+    if (c->scheme != LBM_SCHEME_MOMENT || c->species != 1)
+        return fail(c, LBM_ESTATE, "adjoint_step: one-species moment scheme only");
+    c->err.clear();
+    DeviceGuard g(c->device);
+    hipError_t e = lbm::launch_adjoint_step(c, state, lam_next, lam_out, dtau_accum);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
+    return LBM_OK;
+}
+
 int64_t lbm_steps_done(const lbm_ctx *c) { return c ? c->steps : -1; }
 
 } // extern "C"

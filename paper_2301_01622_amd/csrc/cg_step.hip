@@ -9,8 +9,8 @@
 // Per source node y (tile plus one-node halo):
 //   phi   = (rho1 - rho2)/rho on a radius-2 footprint, kept in LDS for the
 //           three planes z-1, z, z+1 (computed one plane ahead);
-//   G     = (1/c_s^2) sum_i w_i c_i phi(y + c_i),  n = G / max(|G|, 1e-3);
-//   S'    = (1 - omega) S + omega j j/rho + (A/9)(G G/|G| - |G| I)  (collision
+//   G     = (1/c_s^2) sum_i w_i c_i phi(y + c_i),  D = sqrt(|G|^2 + 1e-6),  n = G/D;
+//   S'    = (1 - omega) S + omega j j/rho + (A/9)(G G - |G|^2 I)/D  (collision
 //           plus the second moment of the perturbation operator);
 //   h~_i  = w_i [T + 3 c_i.j + 4.5 c_i c_i : S'],  T = dr - 1.5 tr S';
 //   f1_i  = (rho1/rho)(w_i + h~_i) + beta (rho1 rho2/rho) w_i (c_i.n)/|c_i|.
@@ -30,8 +30,9 @@
 namespace lbm {
 namespace {
 
-// Recolouring direction n = G / max(|G|, kEpsG): the unit normal on every
-// interface, fading continuously to zero where the gradient vanishes.
+// Smoothed gradient norm D = sqrt(|G|^2 + kEpsG^2): n = G/D is the unit
+// normal on every interface and fades smoothly to zero where the gradient
+// vanishes; the perturbation uses the same D.
 constexpr double kEpsG = 1e-3;
 
 template <class R>
@@ -178,15 +179,13 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
                     if (cz != 0) Gz = cz > 0 ? Gz + wphi : Gz - wphi;
                 }
         const R G2 = fma_(Gx, Gx, fma_(Gy, Gy, Gz * Gz));
-        const R Gn = sqrt_<R>(G2);
-        const R invG = G2 > R(0) ? R(1) / Gn : R(0);           // perturbation: 1/|G|
-        const R invD = R(1) / (Gn > R(kEpsG) ? Gn : R(kEpsG));  // recolouring: 1/max(|G|, eps)
+        const R invD = R(1) / sqrt_<R>(G2 + R(kEpsG * kEpsG));
         const R nx = Gx * invD, ny = Gy * invD, nz = Gz * invD;
 
         const R dr = v.v[0], r1 = v.v[1];
         Collided<R> c = collide<R>(dr, v.v[2], v.v[3], v.v[4], v.v[5], v.v[6], v.v[7], v.v[8], v.v[9], v.v[10], omega);
-        // Perturbation: A/9 (G G/|G| - |G| I).
-        const R a9 = A9 * invG;
+        // Perturbation: A/9 (G G - |G|^2 I)/D.
+        const R a9 = A9 * invD;
         c.sxx = fma_(a9, fma_(Gx, Gx, -G2), c.sxx);
         c.syy = fma_(a9, fma_(Gy, Gy, -G2), c.syy);
         c.szz = fma_(a9, fma_(Gz, Gz, -G2), c.szz);

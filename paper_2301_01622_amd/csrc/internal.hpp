@@ -36,6 +36,10 @@ hipError_t launch_moment_step(const lbm_ctx *c, const void *in, void *out);
 // Moment scheme, two species (colour gradient).
 hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out);
 
+// Discrete adjoint of the one-species moment step.
+hipError_t launch_adjoint_step(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out,
+                               double *dtau_accum);
+
 // Population scheme.
 hipError_t launch_population_step(const lbm_ctx *c, const void *in, void *out);
 

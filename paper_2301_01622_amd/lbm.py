@@ -144,6 +144,27 @@ class LBM:
         assert buf.is_cuda and buf.numel() * buf.element_size() >= self.state_bytes
         _lib.check(self._lib.lbm_load_state(self._ctx, ctypes.c_void_p(buf.data_ptr())), self._ctx, "load_state")
 
+    def step_state(self, src: torch.Tensor, dst: torch.Tensor) -> None:
+        """One step from saved state `src` into buffer `dst` (both state_bytes)."""
+        _lib.check(self._lib.lbm_step_state(self._ctx, ctypes.c_void_p(src.data_ptr()),
+                                            ctypes.c_void_p(dst.data_ptr())), self._ctx, "step_state")
+
+    @property
+    def real_dtype(self):
+        """Arithmetic type of the kernels (the co-state's element type)."""
+        return torch.float64 if self.storage == "f64" else torch.float32
+
+    def adjoint_step(self, state: torch.Tensor, lam_next: torch.Tensor, lam_out: torch.Tensor,
+                     dtau_accum: torch.Tensor | None = None) -> None:
+        """lam_out = (dM(t+1)/dM(t))^T lam_next at the saved state M(t);
+        adds this step's dL/dtau into dtau_accum (one float64 on the device)."""
+        assert lam_next.dtype == self.real_dtype and lam_out.dtype == self.real_dtype
+        assert lam_next.is_contiguous() and lam_out.is_contiguous()
+        dptr = ctypes.c_void_p(dtau_accum.data_ptr()) if dtau_accum is not None else None
+        _lib.check(self._lib.lbm_adjoint_step(self._ctx, ctypes.c_void_p(state.data_ptr()),
+                                              ctypes.c_void_p(lam_next.data_ptr()),
+                                              ctypes.c_void_p(lam_out.data_ptr()), dptr), self._ctx, "adjoint_step")
+
     @property
     def steps_done(self) -> int:
         return int(self._lib.lbm_steps_done(self._ctx))

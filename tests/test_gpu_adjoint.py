@@ -1,0 +1,138 @@
+"""GPU parity of the discrete adjoint (one species) against the oracle's
+adjoint, K-independence of the checkpointed rollout, and a central
+finite-difference check of the rollout gradient."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2301_01622_amd import inputs as I  # noqa: E402
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def mods():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2301_01622_amd import autograd as AG
+    from paper_2301_01622_amd.lbm import LBM
+    return LBM, AG
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_adjoint_step_matches_oracle(mods, oracle, q, storage, tol):
+    LBM, _ = mods
+    shape = (19, 23, 37)
+    _say(f"adjoint step {shape} D3Q{q} {storage}")
+    M = I.random_moments(shape, seed=91)
+    lam = np.random.default_rng(92).standard_normal(M.shape)
+    tau = 0.66
+    ref, dom = oracle.moment_adjoint_step(M, lam, q, tau)
+    sim = LBM((37, 23, 19), q, tau, storage=storage)
+    sim.set_moments(torch.from_numpy(M).cuda())
+    st = sim.new_checkpoint()
+    sim.save_state(st)
+    ln = torch.from_numpy(lam).to(sim.real_dtype).cuda().contiguous()
+    lo = torch.empty_like(ln)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sim.adjoint_step(st, ln, lo, dt)
+    got = lo.double().cpu().numpy()
+    dtau = float(dt.cpu())
+    sim.close()
+    e = _rel(got, ref)
+    _say(f"  rel err {e:.3e}, dL/dtau gpu {dtau:.10e} oracle {-dom / tau ** 2:.10e}")
+    assert e <= tol
+    assert abs(dtau - (-dom / tau ** 2)) <= 10 * tol * abs(dom / tau ** 2)
+
+
+def _loss_weights(shape, seed):
+    return np.random.default_rng(seed).standard_normal((10,) + shape)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 1e-4)])
+def test_rollout_gradient_matches_oracle(mods, oracle, storage, tol):
+    """L = sum(W * M(T)); dL/dM0 and dL/dtau through 13 steps, K = 5."""
+    LBM, AG = mods
+    q, shape, T, tau = 19, (12, 13, 17), 13, 0.7
+    _say(f"rollout gradient {shape} {storage} T={T} K=5")
+    M0 = I.random_moments(shape, seed=93, drho=0.01, dj=0.01, dp=0.003)
+    W = _loss_weights(shape, 94)
+    lam0, dL_dtau = oracle.moment_rollout_gradient(M0, W, q, tau, T)
+    sim = LBM((17, 13, 12), q, tau, storage=storage)
+    m0 = torch.from_numpy(M0).cuda().requires_grad_(True)
+    t = torch.tensor(tau, dtype=torch.float64, device="cuda", requires_grad=True)
+    MT = AG.rollout(sim, m0, t, T, K=5)
+    (MT * torch.from_numpy(W).cuda()).sum().backward()
+    g = m0.grad.cpu().numpy()
+    gt = float(t.grad.cpu())
+    sim.close()
+    e = _rel(g, lam0)
+    _say(f"  rel err dM0 {e:.3e}; dL/dtau gpu {gt:.8e} oracle {dL_dtau:.8e}")
+    assert e <= tol
+    assert abs(gt - dL_dtau) <= tol * abs(dL_dtau)
+
+
+def test_rollout_independent_of_checkpoint_interval(mods):
+    LBM, AG = mods
+    shape, T, tau = (16, 16, 16), 24, 0.75
+    M0 = I.random_moments(shape, seed=95, drho=0.01, dj=0.01, dp=0.003)
+    W = torch.from_numpy(_loss_weights(shape, 96)).cuda()
+    grads = []
+    for K in (1, 5, 24):
+        sim = LBM((16, 16, 16), 27, tau, storage="f32")
+        m0 = torch.from_numpy(M0).cuda().requires_grad_(True)
+        t = torch.tensor(tau, dtype=torch.float64, device="cuda", requires_grad=True)
+        (AG.rollout(sim, m0, t, T, K=K) * W).sum().backward()
+        grads.append((m0.grad.cpu().numpy(), float(t.grad)))
+        sim.close()
+    for g, gt in grads[1:]:
+        np.testing.assert_array_equal(g, grads[0][0])
+        assert gt == grads[0][1]
+
+
+def test_rollout_gradient_finite_differences(mods):
+    """32^3 D3Q19 FP32, 60 steps, checkpoints every 20: gradient of the
+    kinetic energy of a target region with respect to the initial velocity
+    (along a seeded solenoidal direction) and to tau, against central
+    differences with h = 1e-3 computed with the GPU forward step."""
+    LBM, AG = mods
+    n, T, K, tau = 32, 60, 20, 0.8
+    _say("finite-difference check 32^3 D3Q19 f32 T=60 K=20")
+    rho, u0 = I.random_solenoidal_box(n, seed=I.SEED_C5, umax=0.02)
+    d = I.solenoidal((n, n, n), seed=I.SEED_C5 + 1, umax=1.0)
+    mask = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    mask[8:24, 8:24, 8:24] = 1.0
+    rho_t = torch.from_numpy(rho).cuda()
+
+    def loss_of(u, t, grad=False):
+        sim = LBM((n, n, n), 19, float(t), storage="f32")
+        u = torch.from_numpy(u).cuda().requires_grad_(grad)
+        tt = torch.tensor(float(t), dtype=torch.float64, device="cuda", requires_grad=grad)
+        M0 = AG.equilibrium_moments(rho_t, u)
+        MT = AG.rollout(sim, M0, tt, T, K=K)
+        L = (mask * (MT[1] ** 2 + MT[2] ** 2 + MT[3] ** 2) / MT[0]).sum()
+        if grad:
+            L.backward()
+            out = (float(L), u.grad.cpu().numpy(), float(tt.grad))
+        else:
+            out = float(L)
+        sim.close()
+        return out
+
+    L0, gu, gt = loss_of(u0, tau, grad=True)
+    h = 1e-3
+    fd_u = (loss_of(u0 + h * d, tau) - loss_of(u0 - h * d, tau)) / (2 * h)
+    fd_t = (loss_of(u0, tau + h) - loss_of(u0, tau - h)) / (2 * h)
+    ad_u = float(np.sum(gu * d))
+    _say(f"  dL/du.d adjoint {ad_u:.6e} fd {fd_u:.6e};  dL/dtau adjoint {gt:.6e} fd {fd_t:.6e}")
+    assert abs(ad_u - fd_u) <= 1e-2 * abs(fd_u)
+    assert abs(gt - fd_t) <= 1e-2 * abs(fd_t)
