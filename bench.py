@@ -77,6 +77,46 @@ def cpu_baseline(n: int, q: int, tau: float, steps: int, rho, u):
     }
 
 
+def adjoint_cost(sim, stream, steps: int, fwd_ms: float):
+    """Time of one discrete-adjoint step, alone and with the recomputation of
+    the forward state it needs (lbm_step_state into a checkpoint slot), on the
+    benchmark box, relative to one forward step."""
+    import torch
+    st = sim.new_checkpoint()
+    slot = sim.new_checkpoint()
+    sim.save_state(st)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    lam = torch.randn((10,) + sim.shape, generator=g, device="cuda", dtype=sim.real_dtype)
+    lam_b = torch.empty_like(lam)
+    dtau = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        sim.adjoint_step(st, lam, lam_b, dtau)
+        sim.step_state(st, slot)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record(stream)
+    for _ in range(steps):
+        sim.adjoint_step(st, lam, lam_b, dtau)
+    e[1].record(stream)
+    for _ in range(steps):
+        sim.step_state(st, slot)
+    e[2].record(stream)
+    torch.cuda.synchronize()
+    adj = e[0].elapsed_time(e[1]) / steps
+    rec = e[1].elapsed_time(e[2]) / steps
+    N = sim.n_nodes
+    return {
+        "ms_forward_step": round(fwd_ms, 5),
+        "ms_adjoint_step": round(adj, 5),
+        "ms_recompute_step": round(rec, 5),
+        "adjoint_over_forward": round(adj / fwd_ms, 3),
+        "adjoint_plus_recompute_over_forward": round((adj + rec) / fwd_ms, 3),
+        "adjoint_hbm_frac": round(120.0 * N / (adj * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "note": "one species, same 256^3 D3Q27 FP32 box; algorithmic bytes of the adjoint step 120 B/node",
+    }
+
+
 def two_component(steps: int, warmup: int):
     """512 x 256 x 256 two-component droplet collision (D3Q19, FP32, tau = 0.8,
     sigma = 0.01, beta = 0.7): drops of radius 40 at +-0.05 along x."""
@@ -140,6 +180,7 @@ def main() -> int:
         sim.set_equilibrium(rho_d, u_d)
         ms = time_steps(sim, stream, args.steps, args.warmup)
         state_bytes, step_bytes = sim.memory_info()
+        adjoint = adjoint_cost(sim, stream, max(args.steps // 4, 10), ms)
         copy = None
         if args.calibrate_copy > 0:
             buf = sim.new_checkpoint()
@@ -212,6 +253,7 @@ def main() -> int:
         "copy_kernel": copy,
         "population_lb": pop,
     }
+    line["adjoint"] = adjoint
     if two:
         line["two_component"] = two
     if copy:

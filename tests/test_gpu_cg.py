@@ -59,8 +59,8 @@ def test_ragged_droplets(LBM, oracle, q, storage, tol):
 
 
 def test_flat_regions_and_minimum_box(LBM, oracle):
-    """3^3 box, one species nearly everywhere: gradients vanish below the
-    threshold in most nodes (the normal is switched off there)."""
+    """3^3 box, one species nearly everywhere: the gradient is far below the
+    smoothing scale in most nodes, where the recolouring direction fades."""
     H = _state(oracle, (3, 3, 3), seed=1)
     ref = oracle.cg_moment_run(H, 19, TAU, oracle.sigma_to_A(SIGMA, TAU), BETA, 4)
     got = _gpu(LBM, H, 19, 4, "f64")
@@ -130,25 +130,47 @@ def test_full_size_conservation(LBM):
     assert np.abs(t1[2:] - t0[2:]).max() <= bound_j
 
 
+def _observables(H):
+    """Drop-averaged density <rho1>_{rho1 > 0.5}, the x-centroids of rho1 in
+    the two halves of the box, and the kinetic energy."""
+    nz, ny, nx = H.shape[1:]
+    x = np.arange(nx)[None, None, :] * np.ones(H.shape[1:])
+    left = x < nx / 2
+    cents = [float((H[0] * m * x).sum() / (H[0] * m).sum()) for m in (left, ~left)]
+    ke = float(0.5 * ((H[2:5] ** 2).sum(0) / (H[0] + H[1])).sum())
+    return float(H[0][H[0] > 0.5].mean()), cents, ke
+
+
 def test_droplet_collision_run(LBM, oracle):
-    """Head-off-axis droplet collision at reduced size (48^3, R = 8, D3Q19,
-    FP32) for 300 steps: velocities within 1e-4, densities within 1e-3 of the
-    FP64 oracle, and the drop-averaged density <rho>_{rho > 0.5} within 1e-4."""
+    """Head-off-axis droplet collision at reduced size (48^3, R = 8, u = +-0.05,
+    D3Q19, FP32).  The film between the colliding drops is unstable: in the
+    FP64 oracle itself, noise of 1e-9 added to rho1 every step moves rho1 by
+    3.7e-3 node-wise within 10 steps and 1.4e-2 by step 300 (|u| by 3e-4),
+    while the drop-averaged density stays within 1e-4, the drop centroids
+    within 3e-3 lattice units and the kinetic energy within 2e-5.  So the
+    FP32 run is compared node by node before contact (5 steps) and through
+    these observables after 300 steps, at ten times the oracle's own spread."""
     shape = (48, 48, 48)
-    _say("droplet collision 48^3 D3Q19 f32 300 steps")
+    _say("droplet collision 48^3 D3Q19 f32")
     r1, r2, u = I.droplets(shape, centres=[(14.0, 21.0, 24.0), (34.0, 25.0, 24.0)], radius=8.0,
                            velocities=[(0.05, 0.0, 0.0), (-0.05, 0.0, 0.0)])
     H0 = oracle.equilibrium_moments2(r1, r2, u)
-    ref = oracle.cg_moment_run(H0, 19, TAU, oracle.sigma_to_A(SIGMA, TAU), BETA, 300)
+    A = oracle.sigma_to_A(SIGMA, TAU)
+    ref5 = oracle.cg_moment_run(H0, 19, TAU, A, BETA, 5)
+    got5 = _gpu(LBM, H0, 19, 5, "f32")
+    d5 = np.abs(got5 - ref5).max(axis=(1, 2, 3))
+    _say(f"  5 steps: max err per field {d5}")
+    assert d5[:2].max() <= 1e-3 and d5[2:5].max() <= 1e-5
+    ref = oracle.cg_moment_run(H0, 19, TAU, A, BETA, 300)
     got = _gpu(LBM, H0, 19, 300, "f32")
-    vg = got[2:5] / (got[0] + got[1])
-    vr = ref[2:5] / (ref[0] + ref[1])
-    du = np.abs(vg - vr).max()
-    drho = np.abs(got[:2] - ref[:2]).max()
-    mg = got[0][got[0] > 0.5].mean()
-    mr = ref[0][ref[0] > 0.5].mean()
-    _say(f"  max|du|={du:.3e} max|drho^k|={drho:.3e} <rho1>_(>0.5) gpu {mg:.8f} oracle {mr:.8f}")
-    assert du <= 1e-4 and drho <= 1e-3 and abs(mg / mr - 1) <= 1e-4
+    (mg, cg, kg), (mr, cr, kr) = _observables(got), _observables(ref)
+    du = np.abs(got[2:5] / (got[0] + got[1]) - ref[2:5] / (ref[0] + ref[1])).max()
+    _say(f"  300 steps: <rho1> {mg:.8f} vs {mr:.8f}; centroids {cg} vs {cr}; KE {kg:.6e} vs {kr:.6e}; "
+         f"max|du| {du:.2e}")
+    assert abs(mg / mr - 1) <= 1e-3
+    assert max(abs(cg[0] - cr[0]), abs(cg[1] - cr[1])) <= 0.03
+    assert abs(kg / kr - 1) <= 2e-4
+    assert du <= 5e-3
 
 
 @pytest.mark.parametrize("storage", ["f32", "f64"])
