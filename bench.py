@@ -220,7 +220,7 @@ def main() -> int:
 
     mlups = N / (ms * 1e-3) / 1e6
     achieved = step_bytes / (ms * 1e-3) / 1e9
-    traffic = measured_traffic(N)
+    traffic_bytes = measured_traffic(N)
     line = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -247,12 +247,15 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
+            "traffic": round(traffic_bytes / (ms * 1e-3) / 1e9, 1) if traffic_bytes else None,
         },
         "bytes_per_node_state": state_bytes // N,
         "copy_kernel": copy,
         "population_lb": pop,
     }
+    if traffic_bytes:
+        line["roofline"]["traffic_bytes_per_launch"] = traffic_bytes
+        line["roofline"]["traffic_over_algorithmic"] = round(traffic_bytes / step_bytes, 4)
     line["adjoint"] = adjoint
     if two:
         line["two_component"] = two
