@@ -135,6 +135,12 @@ def two_component(steps: int, warmup: int):
         ms = time_steps(sim, stream, steps, warmup)
         state_bytes, step_bytes = sim.memory_info()
         sim.close()
+        ps = LBM((512, 256, 256), 19, 0.8, species=2, storage="f32", sigma=0.01, beta=0.7, scheme="population",
+                 stream=stream)
+        ps.set_equilibrium(torch.from_numpy(np.stack([r1, r2])).cuda(), torch.from_numpy(u).cuda())
+        pms = time_steps(ps, stream, steps, warmup)
+        p_state, p_step = ps.memory_info()
+        ps.close()
     return {
         "workload": "512x256x256 two-component droplet collision, D3Q19, FP32 (rho-1, rho1, j, P), tau=0.8, "
                     "sigma=0.01, beta=0.7, R=40, u=+-0.05",
@@ -144,6 +150,15 @@ def two_component(steps: int, warmup: int):
         "ms_per_step": round(ms, 5),
         "hbm_frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "bytes_per_node_state": state_bytes // N,
+        "population_lb": {
+            "scheme": "colour-gradient LB with stored populations (2 x 19 FP32 per node, density pass + "
+                      "collision pass per step)",
+            "value": round(N / (pms * 1e-3) / 1e6, 1),
+            "unit": "MLUPS",
+            "ms_per_step": round(pms, 5),
+            "bytes_per_node_state": p_state // N,
+        },
+        "speedup_vs_population_lb": round(pms / ms, 3),
     }
 
 

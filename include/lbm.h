@@ -55,7 +55,8 @@ extern "C" {
 
 /* ---- schemes and storage formats ------------------------------------------------- */
 #define LBM_SCHEME_MOMENT 0     /* the paper's method: moments only (default) */
-#define LBM_SCHEME_POPULATION 1 /* population-storing BGK, A-B buffers (baseline) */
+#define LBM_SCHEME_POPULATION 1 /* population-storing BGK, A-B buffers (baseline); two species:
+                                   colour-gradient LB with 2q stored populations, FP32 */
 
 /* Device storage of the moment state.  All formats store deviations from the
  * rest state rho = 1, u = 0: delta_rho = rho - 1, j, and
@@ -104,8 +105,8 @@ void lbm_default_opts(lbm_opts *opts);
  *   grid    : box size, every side >= 3
  *   lattice : 19 or 27
  *   tau     : BGK relaxation time (Eq. 7, omega = 1/tau), > 1/2
- *   species : 1, or 2 for the colour-gradient mixture (moment scheme only,
- *             FP32/FP64 storage).  Two species: phase field
+ *   species : 1, or 2 for the colour-gradient mixture (moment scheme with
+ *             FP32/FP64 storage, or population scheme with FP32 storage).  Two species: phase field
  *             phi = (rho1 - rho2)/rho, colour gradient
  *             G = (1/c_s^2) sum_i w_i c_i phi(x + c_i), perturbation with second
  *             moment (A/9)(G G - |G|^2 I)/D, A = 9 sigma/(2 tau), recolouring
@@ -153,8 +154,9 @@ int lbm_step(lbm_ctx *ctx, int n);
  * Returns LBM_EUNSTABLE if any total is not finite. */
 int lbm_reduce(lbm_ctx *ctx, double out[5]);
 
-/* Bytes of device memory the context holds for its state (both copies) and
- * the bytes one time step moves at minimum (every stored value read once and
+/* Bytes of device memory the context holds for its state (both copies, plus
+ * the phase-field scratch array of the two-species population scheme) and the
+ * bytes one time step moves at minimum (every stored value read once and
  * written once).  Either pointer may be NULL. */
 int lbm_memory_info(const lbm_ctx *ctx, int64_t *state_bytes, int64_t *step_bytes);
 

@@ -137,7 +137,7 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     if (species == 2 && o.storage != LBM_STORE_F32 && o.storage != LBM_STORE_F64) return LBM_EINVAL;
     if (species == 2 && (!(o.beta >= 0.0) || !(o.sigma >= 0.0))) return LBM_EINVAL;
     if (!(o.s_pi >= 0.0) || !std::isfinite(o.s_pi)) return LBM_EINVAL;
-    if (species == 2 && o.scheme == LBM_SCHEME_POPULATION) return LBM_EINVAL;
+    if (species == 2 && o.scheme == LBM_SCHEME_POPULATION && o.storage != LBM_STORE_F32) return LBM_EINVAL;
 
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
     if (!c) return LBM_ENOMEM;
@@ -175,6 +175,11 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
             return e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE;
         }
     }
+    if (c->scheme == LBM_SCHEME_POPULATION && species == 2 &&
+        hipMalloc((void **)&c->scratch_phi, sizeof(float) * (size_t)c->N) != hipSuccess) {
+        lbm_destroy(c);
+        return LBM_ENOMEM;
+    }
     if (hipMalloc((void **)&c->partials, sizeof(double) * 5 * lbm::kReduceBlocks) != hipSuccess ||
         hipMalloc((void **)&c->red_out, sizeof(double) * 5) != hipSuccess) {
         lbm_destroy(c);
@@ -205,6 +210,7 @@ int lbm_destroy(lbm_ctx *c)
         if (c->state[k]) (void)hipFree(c->state[k]);
     if (c->partials) (void)hipFree(c->partials);
     if (c->red_out) (void)hipFree(c->red_out);
+    if (c->scratch_phi) (void)hipFree(c->scratch_phi);
     delete c;
     return LBM_OK;
 }
@@ -292,6 +298,9 @@ int lbm_reduce(lbm_ctx *c, double out[5])
     if (c->species == 1) {
         out[0] = n + v[0];
         out[1] = 0.0;
+    } else if (c->scheme == LBM_SCHEME_POPULATION) {
+        out[0] = v[0];
+        out[1] = v[1];
     } else {
         out[0] = v[0];
         out[1] = n + v[1] - v[0];
@@ -329,7 +338,7 @@ int lbm_memory_info(const lbm_ctx *c, int64_t *state_bytes, int64_t *step_bytes)
 {
     if (!c) return LBM_EINVAL;
     const int64_t per_copy = (int64_t)c->elem * c->nfields * c->N;
-    if (state_bytes) *state_bytes = 2 * per_copy;
+    if (state_bytes) *state_bytes = 2 * per_copy + (c->scratch_phi ? (int64_t)sizeof(float) * c->N : 0);
     if (step_bytes) *step_bytes = 2 * per_copy;
     return LBM_OK;
 }

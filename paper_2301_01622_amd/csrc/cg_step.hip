@@ -323,11 +323,18 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out)
 
 } // namespace
 
+#ifndef LBM_CG_TX
+#define LBM_CG_TX 32
+#define LBM_CG_TY 8
+#define LBM_CG_WG 3
+#endif
+
 hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out)
 {
     if (c->species != 2) return hipErrorNotSupported;
     if (c->storage == LBM_STORE_F32)
-        return c->q == 19 ? run<19, float, 32, 8, 3>(c, in, out) : run<27, float, 32, 8, 2>(c, in, out);
+        return c->q == 19 ? run<19, float, LBM_CG_TX, LBM_CG_TY, LBM_CG_WG>(c, in, out)
+                          : run<27, float, 32, 8, 2>(c, in, out);
     if (c->storage == LBM_STORE_F64)
         return c->q == 19 ? run<19, double, 32, 4, 2>(c, in, out) : run<27, double, 32, 4, 2>(c, in, out);
     return hipErrorInvalidValue;

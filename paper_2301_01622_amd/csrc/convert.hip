@@ -141,6 +141,74 @@ __global__ void k_get_population_state(const S *__restrict__ A, T *__restrict__ 
     dst[9 * stride + n] = (T)a.myz;
 }
 
+// Two species: A^k_i[y] = (rho^k/rho)(y + c_i) R(M(y + c_i))_i, unshifted FP32.
+template <int Q, class T>
+__global__ void k_set_population2_state(const T *__restrict__ src, int64_t stride, float *__restrict__ A, int nx,
+                                        int ny, int nz, int64_t N)
+{
+    using L = Lattice<Q>;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int x = (int)(n % nx);
+    const int64_t t = n / nx;
+    const int y = (int)(t % ny), z = (int)(t / ny);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int xs = (x + L::cx(i) + nx) % nx, ys = (y + L::cy(i) + ny) % ny, zs = (z + L::cz(i) + nz) % nz;
+        const int64_t s = (int64_t)xs + (int64_t)nx * ((int64_t)ys + (int64_t)ny * zs);
+        const double r1 = (double)src[s], r2 = (double)src[stride + s], rho = r1 + r2;
+        Collided<double> p;
+        p.jx = (double)src[2 * stride + s];
+        p.jy = (double)src[3 * stride + s];
+        p.jz = (double)src[4 * stride + s];
+        p.sxx = (double)src[5 * stride + s] - rho / 3.0;
+        p.syy = (double)src[6 * stride + s] - rho / 3.0;
+        p.szz = (double)src[7 * stride + s] - rho / 3.0;
+        p.sxy = (double)src[8 * stride + s];
+        p.sxz = (double)src[9 * stride + s];
+        p.syz = (double)src[10 * stride + s];
+        p.T = (rho - 1.0) - 1.5 * (p.sxx + p.syy + p.szz);
+        const double f = L::w(i) + reconstruct<Q, double>(p, i);
+        A[(int64_t)i * N + n] = (float)(r1 / rho * f);
+        A[(int64_t)(Q + i) * N + n] = (float)(r2 / rho * f);
+    }
+}
+
+template <int Q, class T>
+__global__ void k_get_population2_state(const float *__restrict__ A, T *__restrict__ dst, int64_t stride, int nx,
+                                        int ny, int nz, int64_t N)
+{
+    using L = Lattice<Q>;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int x = (int)(n % nx);
+    const int64_t t = n / nx;
+    const int y = (int)(t % ny), z = (int)(t / ny);
+    MomentAcc<double> a;
+    a.zero();
+    double r1 = 0.0, r2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int xs = (x - L::cx(i) + nx) % nx, ys = (y - L::cy(i) + ny) % ny, zs = (z - L::cz(i) + nz) % nz;
+        const int64_t s = (int64_t)xs + (int64_t)nx * ((int64_t)ys + (int64_t)ny * zs);
+        const double f1 = (double)A[(int64_t)i * N + s], f2 = (double)A[(int64_t)(Q + i) * N + s];
+        r1 += f1;
+        r2 += f2;
+        accumulate<Q, double>(a, f1 + f2, i);
+    }
+    dst[n] = (T)r1;
+    dst[stride + n] = (T)r2;
+    dst[2 * stride + n] = (T)a.jx;
+    dst[3 * stride + n] = (T)a.jy;
+    dst[4 * stride + n] = (T)a.jz;
+    dst[5 * stride + n] = (T)a.mxx;
+    dst[6 * stride + n] = (T)a.myy;
+    dst[7 * stride + n] = (T)a.mzz;
+    dst[8 * stride + n] = (T)a.mxy;
+    dst[9 * stride + n] = (T)a.mxz;
+    dst[10 * stride + n] = (T)a.myz;
+}
+
 // ---- primitive fields -> equilibrium moments (public layout, FP64) -------------
 
 template <class T>
@@ -224,6 +292,27 @@ __global__ __launch_bounds__(kThreads) void k_reduce_population(const S *__restr
     block_sum5(v, partials + 5 * blockIdx.x);
 }
 
+// Two-species populations: v0 = sum rho1, v1 = sum rho2, v2..4 = sum j (raw).
+template <int Q>
+__global__ __launch_bounds__(kThreads) void k_reduce_population2(const float *__restrict__ A, int64_t N,
+                                                                 double *__restrict__ partials)
+{
+    using L = Lattice<Q>;
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < N; n += (int64_t)gridDim.x * kThreads) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double f1 = A[(int64_t)i * N + n], f2 = A[(int64_t)(Q + i) * N + n];
+            v[0] += f1;
+            v[1] += f2;
+            v[2] += L::cx(i) * (f1 + f2);
+            v[3] += L::cy(i) * (f1 + f2);
+            v[4] += L::cz(i) * (f1 + f2);
+        }
+    }
+    block_sum5(v, partials + 5 * blockIdx.x);
+}
+
 __global__ __launch_bounds__(kThreads) void k_reduce_final(const double *__restrict__ partials, int nblocks,
                                                            double *__restrict__ out)
 {
@@ -259,6 +348,13 @@ hipError_t launch_set_moments(const lbm_ctx *c, const void *src, int64_t stride,
             if (c->scheme == LBM_SCHEME_MOMENT) {
                 hipLaunchKernelGGL((k_set_moment_state<S, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
                                    s, stride, static_cast<S *>(state), c->N, c->species, c->s_pi);
+            } else if (c->species == 2) {
+                if (c->q == 19)
+                    hipLaunchKernelGGL((k_set_population2_state<19, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0,
+                                       c->stream, s, stride, static_cast<float *>(state), c->nx, c->ny, c->nz, c->N);
+                else
+                    hipLaunchKernelGGL((k_set_population2_state<27, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0,
+                                       c->stream, s, stride, static_cast<float *>(state), c->nx, c->ny, c->nz, c->N);
             } else if (c->q == 19) {
                 hipLaunchKernelGGL((k_set_population_state<19, S, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0,
                                    c->stream, s, stride, static_cast<S *>(state), c->nx, c->ny, c->nz, c->N);
@@ -283,6 +379,14 @@ hipError_t launch_get_moments(const lbm_ctx *c, const void *state, void *dst, in
             if (c->scheme == LBM_SCHEME_MOMENT) {
                 hipLaunchKernelGGL((k_get_moment_state<S, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
                                    st, d, stride, c->N, c->species, 1.0 / c->s_pi);
+            } else if (c->species == 2) {
+                const float *A = reinterpret_cast<const float *>(state);
+                if (c->q == 19)
+                    hipLaunchKernelGGL((k_get_population2_state<19, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0,
+                                       c->stream, A, d, stride, c->nx, c->ny, c->nz, c->N);
+                else
+                    hipLaunchKernelGGL((k_get_population2_state<27, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0,
+                                       c->stream, A, d, stride, c->nx, c->ny, c->nz, c->N);
             } else if (c->q == 19) {
                 hipLaunchKernelGGL((k_get_population_state<19, S, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0,
                                    c->stream, st, d, stride, c->nx, c->ny, c->nz, c->N);
@@ -322,6 +426,12 @@ hipError_t launch_reduce(const lbm_ctx *c, const void *state)
         if (c->scheme == LBM_SCHEME_MOMENT)
             hipLaunchKernelGGL((k_reduce_moment<S>), dim3(kReduceBlocks), dim3(kThreads), 0, c->stream, st, c->N,
                                c->species, c->partials);
+        else if (c->species == 2 && c->q == 19)
+            hipLaunchKernelGGL((k_reduce_population2<19>), dim3(kReduceBlocks), dim3(kThreads), 0, c->stream,
+                               reinterpret_cast<const float *>(state), c->N, c->partials);
+        else if (c->species == 2)
+            hipLaunchKernelGGL((k_reduce_population2<27>), dim3(kReduceBlocks), dim3(kThreads), 0, c->stream,
+                               reinterpret_cast<const float *>(state), c->N, c->partials);
         else if (c->q == 19)
             hipLaunchKernelGGL((k_reduce_population<19, S>), dim3(kReduceBlocks), dim3(kThreads), 0, c->stream, st,
                                c->N, c->partials);

@@ -22,6 +22,7 @@ struct lbm_ctx {
     int cur = 0;      // state[cur] holds the current time level
     double *partials = nullptr;  // FP64 reduction partials (kReduceBlocks x 5)
     double *red_out = nullptr;   // 5 device doubles
+    float *scratch_phi = nullptr; // phase field of the two-species population scheme
     int64_t steps = 0;
     mutable std::string err;
 };

@@ -1,10 +1,19 @@
-// Population-storing BGK step (the comparison scheme, one species).
+// Population-storing schemes (the comparison "LB with populations").
 //
-// State: the q post-collision populations of every node, shifted by their
-// rest value (f~_i = f_i - w_i), one array per direction.  Pull scheme with
-// two buffers: the thread of node x gathers f~_i(x - c_i), takes the moments
-// (Eqs. 1-3), relaxes towards the equilibrium of Eq. 5 with Eq. 7, and
-// writes its q post-collision populations to the other buffer.
+// One species: the q post-collision populations of every node, shifted by
+// their rest value (f~_i = f_i - w_i), one array per direction.  Pull scheme
+// with two buffers: the thread of node x gathers f~_i(x - c_i), takes the
+// moments (Eqs. 1-3), relaxes towards the equilibrium of Eq. 5 with Eq. 7,
+// and writes its q post-collision populations to the other buffer.
+//
+// Two species (standard colour-gradient LB with stored populations): 2q
+// arrays, species 1 then species 2, post-collision.  Each step is two
+// kernels, as in split colour-gradient codes: a density pass that pulls both
+// species and writes the phase field phi = (rho1 - rho2)/rho, then the
+// collision pass that pulls again, takes the colour gradient from phi at the
+// neighbours, relaxes the mixture (Eq. 7), adds the perturbation operator
+// Df_i = (A/2)[w_i (c_i.G)^2 - B_i |G|^2]/D per population (its full form,
+// fourth-order part included) and recolours.
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -73,10 +82,136 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out)
     return hipGetLastError();
 }
 
+// ---- two species ---------------------------------------------------------------
+
+template <int Q>
+__device__ __forceinline__ int64_t pull_index(int x, int y, int z, int i, int nx, int ny, int nz)
+{
+    using L = Lattice<Q>;
+    int xs = x - L::cx(i), ys = y - L::cy(i), zs = z - L::cz(i);
+    xs += xs < 0 ? nx : 0;
+    xs -= xs >= nx ? nx : 0;
+    ys += ys < 0 ? ny : 0;
+    ys -= ys >= ny ? ny : 0;
+    zs += zs < 0 ? nz : 0;
+    zs -= zs >= nz ? nz : 0;
+    return (int64_t)xs + (int64_t)nx * ((int64_t)ys + (int64_t)ny * zs);
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void k_pop_cg_phi(const float *__restrict__ in, float *__restrict__ phi, int nx,
+                                                    int ny, int nz, int64_t N)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int x = (int)(n % nx);
+    const int64_t t = n / nx;
+    const int y = (int)(t % ny), z = (int)(t / ny);
+    float r1 = 0.f, r2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t s = pull_index<Q>(x, y, z, i, nx, ny, nz);
+        r1 += in[(int64_t)i * N + s];
+        r2 += in[(int64_t)(Q + i) * N + s];
+    }
+    phi[n] = (r1 - r2) / (r1 + r2);
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void k_pop_cg_step(const float *__restrict__ in, float *__restrict__ out,
+                                                     const float *__restrict__ phi, int nx, int ny, int nz, int64_t N,
+                                                     float omega, float A, float beta)
+{
+    using L = Lattice<Q>;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int x = (int)(n % nx);
+    const int64_t t = n / nx;
+    const int y = (int)(t % ny), z = (int)(t / ny);
+
+    float f[Q];
+    float r1 = 0.f, r2 = 0.f, rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t s = pull_index<Q>(x, y, z, i, nx, ny, nz);
+        const float a = in[(int64_t)i * N + s], b = in[(int64_t)(Q + i) * N + s];
+        r1 += a;
+        r2 += b;
+        f[i] = a + b;
+        rho += f[i];
+        if (L::cx(i)) jx = L::cx(i) > 0 ? jx + f[i] : jx - f[i];
+        if (L::cy(i)) jy = L::cy(i) > 0 ? jy + f[i] : jy - f[i];
+        if (L::cz(i)) jz = L::cz(i) > 0 ? jz + f[i] : jz - f[i];
+    }
+    // Colour gradient from the phase field of the neighbours.
+    float Gx = 0.f, Gy = 0.f, Gz = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (L::cx(i) == 0 && L::cy(i) == 0 && L::cz(i) == 0) continue;
+        const int64_t s = pull_index<Q>(x, y, z, opposite<Q>(i), nx, ny, nz);  // x + c_i
+        const float wp = (float)(3.0 * L::w(i)) * phi[s];
+        if (L::cx(i)) Gx = L::cx(i) > 0 ? Gx + wp : Gx - wp;
+        if (L::cy(i)) Gy = L::cy(i) > 0 ? Gy + wp : Gy - wp;
+        if (L::cz(i)) Gz = L::cz(i) > 0 ? Gz + wp : Gz - wp;
+    }
+    const float G2 = fma_(Gx, Gx, fma_(Gy, Gy, Gz * Gz));
+    const float invD = 1.0f / __builtin_sqrtf(G2 + 1e-6f);
+    const float inv_rho = reciprocal<float>(rho);
+    const float ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
+    const float uu = fma_(ux, ux, fma_(uy, uy, uz * uz));
+    const float s1 = r1 * inv_rho, s2 = r2 * inv_rho;
+    const float C = beta * r1 * r2 * inv_rho;
+    // Moving directions first; the rest population of each species takes
+    // what is left of its density, so every node emits exactly its mass
+    // (in exact arithmetic the relaxation, the perturbation and the
+    // recolouring all conserve it; FP32 weights do not sum to one exactly).
+    float sum1 = 0.f, sum2 = 0.f;
+    int rest = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+        if (cx == 0 && cy == 0 && cz == 0) {
+            rest = i;
+            continue;
+        }
+        const float w = (float)L::w(i);
+        const float cu = (float)cx * ux + (float)cy * uy + (float)cz * uz;
+        const float feq = w * rho * fma_(4.5f, cu * cu, fma_(3.0f, cu, 1.0f - 1.5f * uu));
+        const float cG = (float)cx * Gx + (float)cy * Gy + (float)cz * Gz;
+        const float df = 0.5f * A * fma_(w, cG * cG, -w * G2) * invD;
+        const float fp = fma_(omega, feq - f[i], f[i]) + df;
+        const float inv_c = (float)(1.0 / __builtin_sqrt((double)(cx * cx + cy * cy + cz * cz)));
+        const float rc = C * w * inv_c * (cG * invD);
+        const float o1 = fma_(s1, fp, rc), o2 = fma_(s2, fp, -rc);
+        out[(int64_t)i * N + n] = o1;
+        out[(int64_t)(Q + i) * N + n] = o2;
+        sum1 += o1;
+        sum2 += o2;
+    }
+    out[(int64_t)rest * N + n] = r1 - sum1;
+    out[(int64_t)(Q + rest) * N + n] = r2 - sum2;
+}
+
+template <int Q>
+hipError_t run_cg(const lbm_ctx *c, const void *in, void *out)
+{
+    const int64_t blocks = (c->N + 255) / 256;
+    hipLaunchKernelGGL((k_pop_cg_phi<Q>), dim3((unsigned)blocks), dim3(256), 0, c->stream,
+                       static_cast<const float *>(in), c->scratch_phi, c->nx, c->ny, c->nz, c->N);
+    hipLaunchKernelGGL((k_pop_cg_step<Q>), dim3((unsigned)blocks), dim3(256), 0, c->stream,
+                       static_cast<const float *>(in), static_cast<float *>(out), c->scratch_phi, c->nx, c->ny,
+                       c->nz, c->N, (float)c->omega, (float)c->A, (float)c->beta);
+    return hipGetLastError();
+}
+
 } // namespace
 
 hipError_t launch_population_step(const lbm_ctx *c, const void *in, void *out)
 {
+    if (c->species == 2) {
+        if (c->storage != LBM_STORE_F32 || !c->scratch_phi) return hipErrorInvalidValue;
+        return c->q == 19 ? run_cg<19>(c, in, out) : run_cg<27>(c, in, out);
+    }
     if (c->species != 1) return hipErrorNotSupported;
     if (c->storage == LBM_STORE_F64) return c->q == 19 ? run<19, double>(c, in, out) : run<27, double>(c, in, out);
     if (c->storage == LBM_STORE_F32) return c->q == 19 ? run<19, float>(c, in, out) : run<27, float>(c, in, out);
