@@ -77,7 +77,9 @@ def cpu_baseline(n: int, q: int, tau: float, steps: int, rho, u):
     }
 
 
-def adjoint_cost(sim, stream, steps: int, fwd_ms: float):
+def adjoint_cost(sim, stream, steps: int, fwd_ms: float, algo_bytes: int = 120,
+                 note: str = "one species, same 256^3 D3Q27 FP32 box; algorithmic bytes of the adjoint step "
+                             "120 B/node"):
     """Time of one discrete-adjoint step, alone and with the recomputation of
     the forward state it needs (lbm_step_state into a checkpoint slot), on the
     benchmark box, relative to one forward step."""
@@ -87,7 +89,7 @@ def adjoint_cost(sim, stream, steps: int, fwd_ms: float):
     sim.save_state(st)
     g = torch.Generator(device="cuda")
     g.manual_seed(7)
-    lam = torch.randn((10,) + sim.shape, generator=g, device="cuda", dtype=sim.real_dtype)
+    lam = torch.randn((sim.nfields,) + sim.shape, generator=g, device="cuda", dtype=sim.real_dtype)
     lam_b = torch.empty_like(lam)
     dtau = torch.zeros(1, dtype=torch.float64, device="cuda")
     for _ in range(3):
@@ -112,8 +114,8 @@ def adjoint_cost(sim, stream, steps: int, fwd_ms: float):
         "ms_recompute_step": round(rec, 5),
         "adjoint_over_forward": round(adj / fwd_ms, 3),
         "adjoint_plus_recompute_over_forward": round((adj + rec) / fwd_ms, 3),
-        "adjoint_hbm_frac": round(120.0 * N / (adj * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "note": "one species, same 256^3 D3Q27 FP32 box; algorithmic bytes of the adjoint step 120 B/node",
+        "adjoint_hbm_frac": round(algo_bytes * N / (adj * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "note": note,
     }
 
 
@@ -134,6 +136,10 @@ def two_component(steps: int, warmup: int):
         sim.set_equilibrium(torch.from_numpy(np.stack([r1, r2])).cuda(), torch.from_numpy(u).cuda())
         ms = time_steps(sim, stream, steps, warmup)
         state_bytes, step_bytes = sim.memory_info()
+        adjoint = adjoint_cost(sim, stream, max(steps // 2, 5), ms, algo_bytes=132,
+                               note="two species, same 512x256x256 D3Q19 FP32 box; algorithmic bytes of the "
+                                    "adjoint step 132 B/node (state, co-state in and out); the two kernels move "
+                                    "180 B/node (colour-gradient co-state through HBM)")
         sim.close()
         ps = LBM((512, 256, 256), 19, 0.8, species=2, storage="f32", sigma=0.01, beta=0.7, scheme="population",
                  stream=stream)
@@ -159,6 +165,7 @@ def two_component(steps: int, warmup: int):
             "bytes_per_node_state": p_state // N,
         },
         "speedup_vs_population_lb": round(pms / ms, 3),
+        "adjoint": adjoint,
     }
 
 

@@ -155,7 +155,8 @@ int lbm_step(lbm_ctx *ctx, int n);
 int lbm_reduce(lbm_ctx *ctx, double out[5]);
 
 /* Bytes of device memory the context holds for its state (both copies, plus
- * the phase-field scratch array of the two-species population scheme) and the
+ * the phase-field scratch array of the two-species population scheme and
+ * the colour-gradient co-state buffer of the two-species adjoint) and the
  * bytes one time step moves at minimum (every stored value read once and
  * written once).  Either pointer may be NULL. */
 int lbm_memory_info(const lbm_ctx *ctx, int64_t *state_bytes, int64_t *step_bytes);
@@ -179,21 +180,28 @@ int lbm_load_state(lbm_ctx *ctx, const void *src_device);
  * Errors: LBM_EINVAL, LBM_ESTATE (population scheme), LBM_EDEVICE. */
 int lbm_step_state(lbm_ctx *ctx, const void *src_state, void *dst_state);
 
-/* One reverse step of the discrete adjoint of the one-species moment scheme
- * (the exact transpose of the Jacobian of one step, Eqs. 4-9 and 1-3).
+/* One reverse step of the discrete adjoint of the moment scheme: the exact
+ * transpose of the Jacobian of one step (one species: Eqs. 4-9 and 1-3; two
+ * species: the colour-gradient step of Sec. III.A with the perturbation and
+ * recolouring operators of Sec. III.B, smoothed normal, A held at 9 sigma/(2 tau)).
  *   state_t    : device, the state M(t) the forward step started from, in the
  *                format of lbm_save_state
- *   lam_next   : device, co-state of M(t+1) in the public layout (10 fields of
- *                N values: rho, j, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz), FP64 for
+ *   lam_next   : device, co-state of M(t+1) in the public layout: one species
+ *                10 fields of N values (rho, j, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz),
+ *                two species 11 fields (rho1, rho2, j, P as before); FP64 for
  *                LBM_STORE_F64 contexts, FP32 otherwise
  *   lam_out    : device, receives the co-state of M(t), same layout; must not
  *                overlap lam_next
  *   dtau_accum : device pointer to one double or NULL; the step adds its
- *                contribution to dL/dtau (sum over nodes, FP64, fixed order)
+ *                contribution to dL/dtau (sum over nodes, FP64, fixed order;
+ *                two species: at fixed sigma, so A varies with tau)
  * A stored off-diagonal P component stands for P_ab and P_ba together, so
  * its co-state is the derivative with respect to that one stored value.
- * Asynchronous.  Errors: LBM_EINVAL (NULL), LBM_ESTATE (two species or the
- * population scheme), LBM_EDEVICE. */
+ * Two species: FP32 or FP64 storage only; the first call allocates a device
+ * buffer of 3 N reals for the co-state of the colour gradient, which the
+ * context keeps (LBM_ENOMEM if that fails).  Asynchronous.
+ * Errors: LBM_EINVAL (NULL or aliased), LBM_ESTATE (population scheme, or two
+ * species with FP16/BF16 storage), LBM_ENOMEM, LBM_EDEVICE. */
 int lbm_adjoint_step(lbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out, double *dtau_accum);
 
 /* Number of time steps advanced since creation or the last set_* call. */

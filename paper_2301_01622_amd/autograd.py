@@ -1,8 +1,9 @@
-"""Differentiable rollouts of the moment-only step (one species).
+"""Differentiable rollouts of the moment-only step (one or two species).
 
 ``rollout(sim, M0, tau, nsteps, K)`` returns M(T) after ``nsteps`` steps from
-the public moments ``M0`` (shape (10, nz, ny, nx)); the result carries an
-autograd graph whose backward is the library's discrete adjoint step:
+the public moments ``M0`` (shape (10, nz, ny, nx) for one species, (11, nz,
+ny, nx) for two: rho1, rho2, j, P); the result carries an autograd graph
+whose backward is the library's discrete adjoint step:
 
   forward : the state is saved every K steps (device copies of the stored
             state) while the library advances the fluid;
@@ -14,7 +15,9 @@ autograd graph whose backward is the library's discrete adjoint step:
 Per step of the backward pass the device moves one forward step (recompute)
 plus one adjoint step; no state is copied besides the checkpoints.
 ``tau`` is a 0-d tensor whose value must equal the context's relaxation
-time; its gradient is dL/dtau.  The result does not depend on K (bit for bit).
+time; its gradient is dL/dtau (two species: at fixed surface tension sigma,
+so the perturbation amplitude A = 9 sigma/(2 tau) moves with tau).  The
+result does not depend on K (bit for bit).
 """
 from __future__ import annotations
 
@@ -24,8 +27,10 @@ import torch
 class MomentLBRollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, M0: torch.Tensor, tau: torch.Tensor, sim, nsteps: int, K: int):
-        if sim.species != 1 or sim.scheme != "moment":
-            raise ValueError("rollout: one-species moment scheme only")
+        if sim.scheme != "moment":
+            raise ValueError("rollout: moment scheme only")
+        if M0.shape[0] != (11 if sim.species == 2 else 10):
+            raise ValueError("rollout: M0 must hold the public moment fields of the context")
         if abs(float(tau) - sim.tau) > 1e-12 * sim.tau:
             raise ValueError("rollout: tau must equal the context's relaxation time")
         if nsteps < 1 or K < 1:

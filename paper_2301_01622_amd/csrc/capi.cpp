@@ -211,6 +211,7 @@ int lbm_destroy(lbm_ctx *c)
     if (c->partials) (void)hipFree(c->partials);
     if (c->red_out) (void)hipFree(c->red_out);
     if (c->scratch_phi) (void)hipFree(c->scratch_phi);
+    if (c->scratch_adj) (void)hipFree(c->scratch_adj);
     delete c;
     return LBM_OK;
 }
@@ -338,7 +339,9 @@ int lbm_memory_info(const lbm_ctx *c, int64_t *state_bytes, int64_t *step_bytes)
 {
     if (!c) return LBM_EINVAL;
     const int64_t per_copy = (int64_t)c->elem * c->nfields * c->N;
-    if (state_bytes) *state_bytes = 2 * per_copy + (c->scratch_phi ? (int64_t)sizeof(float) * c->N : 0);
+    if (state_bytes)
+        *state_bytes = 2 * per_copy + (c->scratch_phi ? (int64_t)sizeof(float) * c->N : 0) +
+                       (c->scratch_adj ? 3 * (int64_t)c->elem * c->N : 0);
     if (step_bytes) *step_bytes = 2 * per_copy;
     return LBM_OK;
 }
@@ -389,11 +392,21 @@ int lbm_adjoint_step(lbm_ctx *c, const void *state, const void *lam_next, void *
     if (!c) return LBM_EINVAL;
     if (!state || !lam_next || !lam_out || lam_next == lam_out)
         return fail(c, LBM_EINVAL, "adjoint_step: NULL or aliased buffers");
-    if (c->scheme != LBM_SCHEME_MOMENT || c->species != 1)
-        return fail(c, LBM_ESTATE, "adjoint_step: one-species moment scheme only");
+    if (c->scheme != LBM_SCHEME_MOMENT)
+        return fail(c, LBM_ESTATE, "adjoint_step: moment scheme only");
+    if (c->species == 2 && c->storage != LBM_STORE_F32 && c->storage != LBM_STORE_F64)
+        return fail(c, LBM_ESTATE, "adjoint_step: two species need FP32 or FP64 storage");
     c->err.clear();
     DeviceGuard g(c->device);
-    hipError_t e = lbm::launch_adjoint_step(c, state, lam_next, lam_out, dtau_accum);
+    if (c->species == 2 && !c->scratch_adj) {
+        if (hipMalloc(&c->scratch_adj, 3 * c->elem * (size_t)c->N) != hipSuccess) {
+            c->scratch_adj = nullptr;
+            (void)hipGetLastError();
+            return fail(c, LBM_ENOMEM, "adjoint_step: colour-gradient co-state buffer");
+        }
+    }
+    hipError_t e = c->species == 2 ? lbm::launch_cg_adjoint_step(c, state, lam_next, lam_out, dtau_accum)
+                                   : lbm::launch_adjoint_step(c, state, lam_next, lam_out, dtau_accum);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
     return LBM_OK;
 }

@@ -23,6 +23,7 @@ struct lbm_ctx {
     double *partials = nullptr;  // FP64 reduction partials (kReduceBlocks x 5)
     double *red_out = nullptr;   // 5 device doubles
     float *scratch_phi = nullptr; // phase field of the two-species population scheme
+    void *scratch_adj = nullptr;  // co-state of the colour gradient (3 N reals), two-species adjoint
     int64_t steps = 0;
     mutable std::string err;
 };
@@ -40,6 +41,11 @@ hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out);
 // Discrete adjoint of the one-species moment step.
 hipError_t launch_adjoint_step(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out,
                                double *dtau_accum);
+
+// Discrete adjoint of the two-species (colour-gradient) moment step; uses
+// c->scratch_adj (3 N reals) for the co-state of the colour gradient.
+hipError_t launch_cg_adjoint_step(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out,
+                                  double *dtau_accum);
 
 // Population scheme.
 hipError_t launch_population_step(const lbm_ctx *c, const void *in, void *out);

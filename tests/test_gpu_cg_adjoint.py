@@ -1,0 +1,175 @@
+"""GPU parity of the two-component (colour-gradient) discrete adjoint against
+the oracle's adjoint, K-independence of the checkpointed rollout and a
+finite-difference check of dL/dtau at fixed surface tension.
+
+The co-state of the two-component step grows quickly with the horizon when
+recolouring is on (the film between drops is unstable, see the oracle's
+pins), so rollouts with beta > 0 are short; the long one runs with beta = 0."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2301_01622_amd import inputs as I  # noqa: E402
+
+SIGMA, BETA = 0.01, 0.7
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def mods():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2301_01622_amd import autograd as AG
+    from paper_2301_01622_amd.lbm import LBM
+    return LBM, AG
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def _state(oracle, shape, seed, neq=1e-3, radius=None):
+    nz, ny, nx = shape
+    r1, r2, u = I.droplets(shape, centres=[(nx * 0.3, ny * 0.45, nz * 0.5), (nx * 0.7, ny * 0.55, nz * 0.5)],
+                           radius=radius or min(shape) * 0.25,
+                           velocities=[(0.05, 0.0, 0.0), (-0.05, 0.0, 0.0)])
+    H = oracle.equilibrium_moments2(r1, r2, u)
+    if neq:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        H[5:] += neq * rng.standard_normal(H[5:].shape)
+    return np.ascontiguousarray(H)
+
+
+def _one_step(LBM, H, lam, q, tau, storage, beta=BETA):
+    nf, nz, ny, nx = H.shape
+    sim = LBM((nx, ny, nz), q, tau, species=2, storage=storage, sigma=SIGMA, beta=beta)
+    sim.set_moments(torch.from_numpy(H).cuda())
+    st = sim.new_checkpoint()
+    sim.save_state(st)
+    ln = torch.from_numpy(lam).to(sim.real_dtype).cuda().contiguous()
+    lo = torch.empty_like(ln)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sim.adjoint_step(st, ln, lo, dt)
+    got = lo.double().cpu().numpy()
+    dtau = float(dt.cpu())
+    sim.close()
+    return got, dtau
+
+
+# The rho1/rho2 co-states go through the colour-gradient chain (1/D, 1/D^3
+# with D >= 1e-3): their error is about 200 units of rounding in either
+# precision (FP64 2.3e-14, FP32 1.0e-5 relative to the largest co-state on
+# the D3Q27 case).  The bounds are 1000 units: 1000 * 2^-53 and 1000 * 2^-24.
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("storage,tol", [("f64", 1000 * 2.0 ** -53), ("f32", 1000 * 2.0 ** -24)])
+def test_cg_adjoint_step_matches_oracle(mods, oracle, q, storage, tol):
+    """Ragged box (37 x 23 x 19: several 32 x 8 tiles with partial ones),
+    two drops with a non-equilibrium part, random co-state."""
+    LBM, _ = mods
+    shape, tau = (19, 23, 37), 0.8
+    _say(f"two-component adjoint step {shape} D3Q{q} {storage}")
+    H = _state(oracle, shape, seed=31)
+    lam = np.random.default_rng(32).standard_normal(H.shape)
+    ref, dref = oracle.cg_adjoint_step(H, lam, q, tau, SIGMA, BETA)
+    got, dtau = _one_step(LBM, H, lam, q, tau, storage)
+    err = np.abs(got - ref).max(axis=(1, 2, 3)) / np.abs(ref).max()
+    _say(f"  rel err per field {err}; dL/dtau gpu {dtau:.10e} oracle {dref:.10e}")
+    assert err.max() <= tol
+    assert abs(dtau - dref) <= 10 * tol * abs(dref)
+
+
+def test_cg_adjoint_step_minimum_box_and_no_recolouring(mods, oracle):
+    """3^3 box (every stencil wraps several times) and beta = 0."""
+    LBM, _ = mods
+    for shape, beta in (((3, 3, 3), BETA), ((7, 9, 11), 0.0)):
+        H = _state(oracle, shape, seed=33, radius=1.2 if shape[0] == 3 else None)
+        lam = np.random.default_rng(34).standard_normal(H.shape)
+        ref, dref = oracle.cg_adjoint_step(H, lam, 19, 0.7, SIGMA, beta)
+        got, dtau = _one_step(LBM, H, lam, 19, 0.7, "f64", beta=beta)
+        _say(f"  {shape} beta={beta}: rel err {_rel(got, ref):.3e}")
+        assert _rel(got, ref) <= 1e-12
+        assert abs(dtau - dref) <= 1e-11 * abs(dref)
+
+
+def _loss_weights(shape, seed):
+    return np.random.default_rng(seed).standard_normal((11,) + shape)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_cg_rollout_gradient_matches_oracle(mods, oracle, storage, tol):
+    """L = sum(W * M(T)); dL/dM0 and dL/dtau through 5 steps with K = 2 (a
+    checkpoint boundary inside the rollout), against the oracle's rollout."""
+    LBM, AG = mods
+    q, shape, T, tau = 19, (12, 13, 17), 5, 0.8
+    _say(f"two-component rollout gradient {shape} {storage} T={T} K=2")
+    H0 = _state(oracle, shape, seed=35)
+    W = _loss_weights(shape, 36)
+    lam0, dref = oracle.cg_rollout_gradient(H0, W, q, tau, SIGMA, BETA, T)
+    sim = LBM((17, 13, 12), q, tau, species=2, storage=storage, sigma=SIGMA, beta=BETA)
+    m0 = torch.from_numpy(H0).cuda().requires_grad_(True)
+    t = torch.tensor(tau, dtype=torch.float64, device="cuda", requires_grad=True)
+    MT = AG.rollout(sim, m0, t, T, K=2)
+    (MT * torch.from_numpy(W).cuda()).sum().backward()
+    g = m0.grad.cpu().numpy()
+    gt = float(t.grad.cpu())
+    sim.close()
+    e = _rel(g, lam0)
+    _say(f"  rel err dM0 {e:.3e}; dL/dtau gpu {gt:.8e} oracle {dref:.8e}")
+    assert e <= tol
+    assert abs(gt - dref) <= tol * abs(dref)
+
+
+def test_cg_rollout_independent_of_K(mods, oracle):
+    LBM, AG = mods
+    shape, T = (12, 13, 17), 6
+    H0 = _state(oracle, shape, seed=37)
+    W = torch.from_numpy(_loss_weights(shape, 38)).cuda()
+    out = []
+    for K in (1, 4, 6):
+        sim = LBM((17, 13, 12), 19, 0.8, species=2, storage="f32", sigma=SIGMA, beta=BETA)
+        m0 = torch.from_numpy(H0).cuda().requires_grad_(True)
+        t = torch.tensor(0.8, dtype=torch.float64, device="cuda", requires_grad=True)
+        (AG.rollout(sim, m0, t, T, K=K) * W).sum().backward()
+        out.append((m0.grad.cpu().numpy(), float(t.grad.cpu())))
+        sim.close()
+    for g, gt in out[1:]:
+        np.testing.assert_array_equal(g, out[0][0])
+        assert gt == out[0][1]
+
+
+def test_cg_tau_gradient_finite_difference(mods, oracle):
+    """dL/dtau at fixed sigma from the adjoint against a central difference of
+    the GPU forward run (FP64), 30 steps without recolouring: the drops relax
+    under surface tension, the loss is the kinetic energy plus the
+    rho1-weighted second moment of position."""
+    LBM, AG = mods
+    shape, T, tau, h = (16, 16, 16), 30, 0.8, 1e-5
+    H0 = _state(oracle, shape, seed=39, neq=0.0, radius=4.0)
+    z, y, x = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
+    X2 = torch.from_numpy((x - 8.0) ** 2 + (y - 8.0) ** 2 + (z - 8.0) ** 2).cuda()
+
+    def loss(M):
+        rho = M[0] + M[1]
+        return 0.5 * (M[2:5] ** 2).sum(0).div(rho).sum() + 1e-3 * (M[0] * X2).sum()
+
+    sim = LBM((16, 16, 16), 19, tau, species=2, storage="f64", sigma=SIGMA, beta=0.0)
+    m0 = torch.from_numpy(H0).cuda()
+    t = torch.tensor(tau, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss(AG.rollout(sim, m0, t, T, K=10)).backward()
+    gt = float(t.grad.cpu())
+    sim.close()
+    vals = []
+    for tt in (tau + h, tau - h):
+        s = LBM((16, 16, 16), 19, tt, species=2, storage="f64", sigma=SIGMA, beta=0.0)
+        s.set_moments(m0)
+        s.step(T)
+        vals.append(float(loss(s.get_moments(torch.float64))))
+        s.close()
+    fd = (vals[0] - vals[1]) / (2 * h)
+    _say(f"  dL/dtau adjoint {gt:.10e} central difference {fd:.10e}")
+    assert abs(gt - fd) <= 1e-6 * abs(fd)
