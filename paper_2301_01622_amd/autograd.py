@@ -84,3 +84,14 @@ def equilibrium_moments(rho: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
     rows = [rho] + [rho * u[a] for a in range(3)]
     rows += [rho * u[a] * u[b] + (rho / 3.0 if a == b else 0.0) for a, b in pairs]
     return torch.stack(rows, dim=0)
+
+
+def equilibrium_moments2(rho1: torch.Tensor, rho2: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+    """Two-species public moments (rho1, rho2, j, P) with zero non-equilibrium
+    part from the species densities and a shared velocity, as differentiable
+    torch operations: rho = rho1 + rho2, j = rho u, P = rho c_s^2 I + rho u u."""
+    rho = rho1 + rho2
+    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    rows = [rho1, rho2] + [rho * u[a] for a in range(3)]
+    rows += [rho * u[a] * u[b] + (rho / 3.0 if a == b else 0.0) for a, b in pairs]
+    return torch.stack(rows, dim=0)

@@ -1,0 +1,139 @@
+"""Gradients of the droplet-centroid loss through a two-component rollout
+(128^3, D3Q19, FP32, tau = 0.8, sigma = 0.01, beta = 0.7, two drops of
+radius 20 at +-0.05 along x offset 0.5 R in y, 400 steps, checkpoint every
+20): the adjoint's dL/du0 (along a seeded solenoidal direction) and dL/dtau
+at fixed sigma against central differences with h = 1e-3, and, on a 32^3
+box, the whole dL/du0 field against the oracle's discrete adjoint.
+
+Loss: L = sum_k (c_k(T) - c_k*)^2, c_k the x-centroid of rho1 over the half
+box H_k (H_1 = {x < L/2}, H_2 its complement; fixed masks), targets
+c_k* = c_k(0) +- 10 towards the mid-plane.
+
+Conditioning: with recolouring, the linearised step amplifies short waves
+wherever the minority species is present at more than about 1e-4 and the
+colour gradient is below the smoothing scale of the normal (there the
+recolouring acts as anti-diffusion of the minority species).  The drops of
+radius 20 keep the minority below 1e-11 in their cores, and the loss is
+smooth: the C5 gradient matches central differences.  A 32^3 box cannot hold
+two such drops, so the oracle comparison uses one drop of radius 8 (minority
+>= 2e-5 in its core), where the oracle's own adjoint matches its central
+differences to 4e-8 over 100 steps; two drops of radius 5 or 6 at 32^3 are
+not differentiable in this sense (co-state 1e4 to 1e16 after 30 steps)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2301_01622_amd import inputs as I  # noqa: E402
+
+TAU, SIGMA, BETA = 0.8, 0.01, 0.7
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def mods():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2301_01622_amd import autograd as AG
+    from paper_2301_01622_amd.lbm import LBM
+    return LBM, AG
+
+
+class Centroids:
+    """x-centroids of rho1 over fixed masks and their squared distances to
+    targets shifted by `shifts` from the initial centroids."""
+
+    def __init__(self, n, device, shifts, halves=True):
+        x = torch.arange(n, dtype=torch.float64, device=device).view(1, 1, n).expand(n, n, n)
+        self.x = x
+        self.masks = [(x < n / 2).double(), (x >= n / 2).double()] if halves else [torch.ones_like(x)]
+        self.shifts = shifts
+        self.targets = None
+
+    def cents(self, rho1):
+        return [(rho1 * m * self.x).sum() / (rho1 * m).sum() for m in self.masks]
+
+    def set_targets(self, rho1):
+        self.targets = [c.item() + s for c, s in zip(self.cents(rho1), self.shifts)]
+
+    def loss(self, M):
+        return sum((c - t) ** 2 for c, t in zip(self.cents(M[0]), self.targets))
+
+
+def test_c5_gradient_central_differences(mods):
+    LBM, AG = mods
+    n, T, K, h = 128, 400, 20, 1e-3
+    _say(f"C5 gradient {n}^3 FP32 T={T} K={K} h={h}")
+    r1, r2, u0 = I.droplet_collision_128((n, n, n))
+    d = I.solenoidal((n, n, n), seed=16220005, umax=1.0)
+    R1, R2, U0, Dd = (torch.from_numpy(a).cuda() for a in (r1, r2, u0, d))
+    C = Centroids(n, "cuda", (10.0, -10.0))
+    C.set_targets(R1)
+
+    sim = LBM((n, n, n), 19, TAU, species=2, storage="f32", sigma=SIGMA, beta=BETA)
+    u = U0.clone().requires_grad_(True)
+    t = torch.tensor(TAU, dtype=torch.float64, device="cuda", requires_grad=True)
+    L = C.loss(AG.rollout(sim, AG.equilibrium_moments2(R1, R2, u), t, T, K=K))
+    L.backward()
+    g_u = float((u.grad * Dd).sum())
+    g_t = float(t.grad)
+    sim.close()
+
+    def run(uu, tt):
+        s = LBM((n, n, n), 19, tt, species=2, storage="f32", sigma=SIGMA, beta=BETA)
+        s.set_moments(AG.equilibrium_moments2(R1, R2, uu))
+        s.step(T)
+        v = float(C.loss(s.get_moments(torch.float64)))
+        s.close()
+        return v
+
+    fd_u = (run(U0 + h * Dd, TAU) - run(U0 - h * Dd, TAU)) / (2 * h)
+    fd_t = (run(U0, TAU + h) - run(U0, TAU - h)) / (2 * h)
+    _say(f"  L={float(L):.8e}; dL/du0.d adjoint {g_u:.8e} fd {fd_u:.8e}; dL/dtau adjoint {g_t:.8e} fd {fd_t:.8e}")
+    # measured: 2.8e-5 and 5e-6 relative
+    assert abs(g_u - fd_u) <= 1e-3 * abs(fd_u)
+    assert abs(g_t - fd_t) <= 1e-3 * abs(fd_t)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_c5_gradient_field_matches_oracle_32(mods, oracle, storage, tol):
+    """One drop of radius 8 moving at 0.05 along x in a 32^3 box, 100 steps,
+    K = 20, loss (c(T) - c(0) - 2.5)^2 of the x-centroid of rho1: the whole
+    dL/du0 field and dL/dtau against the oracle's rollout adjoint (FP64)."""
+    LBM, AG = mods
+    n, T, K = 32, 100, 20
+    r1, r2, u0 = I.droplets((n, n, n), centres=[(16.0, 16.0, 16.0)], radius=8.0, velocities=[(0.05, 0.0, 0.0)])
+    R1, R2, U0 = (torch.from_numpy(a).cuda() for a in (r1, r2, u0))
+    C = Centroids(n, "cuda", (2.5,), halves=False)
+    C.set_targets(R1)
+    sim = LBM((n, n, n), 19, TAU, species=2, storage=storage, sigma=SIGMA, beta=BETA)
+    u = U0.clone().requires_grad_(True)
+    t = torch.tensor(TAU, dtype=torch.float64, device="cuda", requires_grad=True)
+    MT = AG.rollout(sim, AG.equilibrium_moments2(R1, R2, u), t, T, K=K)
+    L = C.loss(MT)
+    L.backward()
+    g_u = u.grad.cpu().numpy()
+    g_t = float(t.grad)
+    # dL/dM(T) from the GPU's final state, then the oracle's adjoint from M0.
+    MTd = MT.detach().double().requires_grad_(True)
+    C.loss(MTd).backward()
+    lam_T = MTd.grad.cpu().numpy()
+    sim.close()
+    M0 = oracle.equilibrium_moments2(r1, r2, u0)
+    lam0, dref = oracle.cg_rollout_gradient(M0, lam_T, 19, TAU, SIGMA, BETA, T)
+    rho = r1 + r2
+    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    ref_u = np.zeros_like(u0)
+    for a in range(3):
+        ref_u[a] += rho * lam0[2 + a]
+    for k, (a, b) in enumerate(pairs):
+        ref_u[a] += rho * u0[b] * lam0[5 + k]
+        ref_u[b] += rho * u0[a] * lam0[5 + k]
+    e = np.abs(g_u - ref_u).max() / np.abs(ref_u).max()
+    _say(f"  32^3 {storage}: rel err dL/du0 {e:.3e}; dL/dtau gpu {g_t:.10e} oracle {dref:.10e}")
+    assert e <= tol
+    assert abs(g_t - dref) <= tol * abs(dref)

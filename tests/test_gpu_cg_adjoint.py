@@ -2,9 +2,11 @@
 the oracle's adjoint, K-independence of the checkpointed rollout and a
 finite-difference check of dL/dtau at fixed surface tension.
 
-The co-state of the two-component step grows quickly with the horizon when
-recolouring is on (the film between drops is unstable, see the oracle's
-pins), so rollouts with beta > 0 are short; the long one runs with beta = 0."""
+With recolouring, the linearised step amplifies short waves wherever the
+minority species is present at more than about 1e-4 and the colour gradient
+is below the smoothing scale of the normal (anti-diffusion of the minority
+species); the small drops used here are in that regime, so rollouts with
+beta > 0 are short and the long one runs with beta = 0."""
 import numpy as np
 import pytest
 
