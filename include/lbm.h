@@ -154,15 +154,20 @@ int lbm_step(lbm_ctx *ctx, int n);
  * Returns LBM_EUNSTABLE if any total is not finite. */
 int lbm_reduce(lbm_ctx *ctx, double out[5]);
 
-/* Bytes of device memory the context holds for its state (both copies, plus
- * the phase-field scratch array of the two-species population scheme and
- * the colour-gradient co-state buffer of the two-species adjoint) and the
- * bytes one time step moves at minimum (every stored value read once and
- * written once).  Either pointer may be NULL. */
+/* Bytes of device memory the context holds for its state (both copies with
+ * the padding of the blocked layout, plus the phase-field scratch array of
+ * the two-species population scheme and the colour-gradient co-state buffer
+ * of the two-species adjoint) and the bytes one time step moves at minimum
+ * (every stored value of every node read once and written once).  Either
+ * pointer may be NULL. */
 int lbm_memory_info(const lbm_ctx *ctx, int64_t *state_bytes, int64_t *step_bytes);
 
 /* Size in bytes of one time level of the stored state (the buffer that
- * lbm_save_state fills).  Errors: LBM_EINVAL. */
+ * lbm_save_state fills).  The moment scheme stores its fields in an internal
+ * blocked layout (the fields of each 64 x 16 block of an xy-plane are
+ * contiguous; nx and ny are rounded up to multiples of 64 and 16), so this is
+ * at least nfields x N x element size; the population scheme stores q (or 2q)
+ * arrays of N values.  Errors: LBM_EINVAL. */
 int lbm_state_bytes(const lbm_ctx *ctx, int64_t *bytes);
 
 /* Copies the current time level of the stored state, in its storage format,

@@ -159,14 +159,15 @@ __global__ __launch_bounds__(TX *TY) void k_adjoint_tile(const S *__restrict__ s
     };
 
     auto finish = [&](int d) {
-        const int64_t o = (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)d * plane;
+        const int64_t o = (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)d * plane;  // public
+        const int64_t so = g.lay.xy(x0 + lx, y0 + ly) + (int64_t)d * g.lay.plane;           // stored
         const MomentAcc<R> &a = acc[0];
-        const R dr = Store<S>::load(state[o]);
-        const R jx = Store<S>::load(state[g.N + o]), jy = Store<S>::load(state[2 * g.N + o]),
-                jz = Store<S>::load(state[3 * g.N + o]);
+        const R dr = Store<S>::load(state[so]);
+        const R jx = Store<S>::load(state[kBlock + so]), jy = Store<S>::load(state[2 * kBlock + so]),
+                jz = Store<S>::load(state[3 * kBlock + so]);
         R s[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) s[k] = Store<S>::load(state[(4 + k) * g.N + o]) * inv_s_pi;
+        for (int k = 0; k < 6; ++k) s[k] = Store<S>::load(state[(4 + k) * kBlock + so]) * inv_s_pi;
         const R inv_rho = R(1) / (R(1) + dr);
         // Gamma = 4.5 sum w c c a - 1.5 alpha I
         const R gxx = fma_(R(4.5), a.mxx, R(-1.5) * a.r), gyy = fma_(R(4.5), a.myy, R(-1.5) * a.r),
@@ -257,6 +258,7 @@ hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *la
     g.ny = c->ny;
     g.nz = c->nz;
     g.N = c->N;
+    g.lay = c->lay;
     g.tiles_x = (c->nx + TX - 1) / TX;
     g.tiles_y = (c->ny + TY - 1) / TY;
     g.zchunk = choose_zchunk(c->nz, g.tiles_x * g.tiles_y, 256 * WG_PER_CU);

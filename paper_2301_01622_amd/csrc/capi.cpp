@@ -159,6 +159,8 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     c->check_every = o.check_every;
     c->elem = storage_bytes(o.storage);
     c->nfields = o.scheme == LBM_SCHEME_MOMENT ? (species == 1 ? 10 : 11) : lattice * species;
+    c->lay = lbm::moment_layout(c->nx, c->ny, c->nfields);
+    c->state_elems = o.scheme == LBM_SCHEME_MOMENT ? c->lay.plane * c->nz : (int64_t)c->nfields * c->N;
 
     if (o.device >= 0) {
         c->device = o.device;
@@ -167,7 +169,7 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
         return LBM_EDEVICE;
     }
     DeviceGuard g(c->device);
-    const size_t bytes = c->elem * (size_t)c->nfields * (size_t)c->N;
+    const size_t bytes = c->elem * (size_t)c->state_elems;
     for (int k = 0; k < 2; ++k) {
         hipError_t e = hipMalloc(&c->state[k], bytes);
         if (e != hipSuccess) {
@@ -338,18 +340,18 @@ int lbm_step(lbm_ctx *c, int n)
 int lbm_memory_info(const lbm_ctx *c, int64_t *state_bytes, int64_t *step_bytes)
 {
     if (!c) return LBM_EINVAL;
-    const int64_t per_copy = (int64_t)c->elem * c->nfields * c->N;
+    const int64_t per_copy = (int64_t)c->elem * c->state_elems;
     if (state_bytes)
         *state_bytes = 2 * per_copy + (c->scratch_phi ? (int64_t)sizeof(float) * c->N : 0) +
                        (c->scratch_adj ? 3 * (int64_t)c->elem * c->N : 0);
-    if (step_bytes) *step_bytes = 2 * per_copy;
+    if (step_bytes) *step_bytes = 2 * (int64_t)c->elem * c->nfields * c->N;
     return LBM_OK;
 }
 
 int lbm_state_bytes(const lbm_ctx *c, int64_t *bytes)
 {
     if (!c || !bytes) return LBM_EINVAL;
-    *bytes = (int64_t)c->elem * c->nfields * c->N;
+    *bytes = (int64_t)c->elem * c->state_elems;
     return LBM_OK;
 }
 
@@ -359,7 +361,7 @@ int lbm_save_state(lbm_ctx *c, void *dst)
     if (!dst) return fail(c, LBM_EINVAL, "save_state: NULL buffer");
     c->err.clear();
     DeviceGuard g(c->device);
-    hipError_t e = lbm::launch_copy(c, c->state[c->cur], dst, (int64_t)c->elem * c->nfields * c->N);
+    hipError_t e = lbm::launch_copy(c, c->state[c->cur], dst, (int64_t)c->elem * c->state_elems);
     if (e != hipSuccess) return hip_fail(c, e, "save_state");
     return LBM_OK;
 }
@@ -370,7 +372,7 @@ int lbm_load_state(lbm_ctx *c, const void *src)
     if (!src) return fail(c, LBM_EINVAL, "load_state: NULL buffer");
     c->err.clear();
     DeviceGuard g(c->device);
-    hipError_t e = lbm::launch_copy(c, src, c->state[c->cur], (int64_t)c->elem * c->nfields * c->N);
+    hipError_t e = lbm::launch_copy(c, src, c->state[c->cur], (int64_t)c->elem * c->state_elems);
     if (e != hipSuccess) return hip_fail(c, e, "load_state");
     return LBM_OK;
 }

@@ -129,22 +129,26 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(const R *__restrict_
     };
     const int64_t own_xy = xy_of(h0);
     const int64_t ring_xy = has_ring ? xy_of(hr) : 0;
-    auto zoff = [&](int p) -> int64_t {
-        const int zs = p < 0 ? p + g.nz : (p >= g.nz ? p - g.nz : p);
-        return (int64_t)zs * plane;
+    // The same nodes in the stored (blocked) layout of the state.
+    auto sxy_of = [&](int h) -> int64_t {
+        return g.lay.xy(wrap_coord(x0 - 1 + h % HX, g.nx), wrap_coord(y0 - 1 + h / HX, g.ny));
     };
+    const int64_t own_sxy = sxy_of(h0);
+    const int64_t ring_sxy = has_ring ? sxy_of(hr) : 0;
+    auto zs_of = [&](int p) { return p < 0 ? p + g.nz : (p >= g.nz ? p - g.nz : p); };
+    auto zoff = [&](int p) -> int64_t { return (int64_t)zs_of(p) * plane; };
     auto ring_slot = [&](int p) { return (p - z0 + 4) & 3; };
 
     // phi of plane p for this thread's nodes (from the stored dr and rho1).
     auto write_phi = [&](int p) {
-        const int64_t zo = zoff(p);
+        const int64_t zo = (int64_t)zs_of(p) * g.lay.plane;
         R *ph = lds_phi + ring_slot(p) * HN;
         {
-            const R dr = state[own_xy + zo], r1 = state[g.N + own_xy + zo];
+            const R dr = state[own_sxy + zo], r1 = state[kBlock + own_sxy + zo];
             ph[h0] = fma_(R(2) * r1, reciprocal<R>(R(1) + dr), R(-1));
         }
         if (has_ring) {
-            const R dr = state[ring_xy + zo], r1 = state[g.N + ring_xy + zo];
+            const R dr = state[ring_sxy + zo], r1 = state[kBlock + ring_sxy + zo];
             ph[hr] = fma_(R(2) * r1, reciprocal<R>(R(1) + dr), R(-1));
         }
     };
@@ -207,14 +211,15 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(const R *__restrict_
     };
 
     auto finish = [&](int dpl) {
-        const int64_t o = (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)dpl * plane;
+        const int64_t o = (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)dpl * plane;  // public
+        const int64_t so = g.lay.xy(x0 + lx, y0 + ly) + (int64_t)dpl * g.lay.plane;           // stored
         const CgAdjAcc<R> &a = acc[0];
         // Own state.
-        const R dr = state[o], r1 = state[g.N + o];
-        const R jx = state[2 * g.N + o], jy = state[3 * g.N + o], jz = state[4 * g.N + o];
+        const R dr = state[so], r1 = state[kBlock + so];
+        const R jx = state[2 * kBlock + so], jy = state[3 * kBlock + so], jz = state[4 * kBlock + so];
         R s[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) s[k] = state[(5 + k) * g.N + o];
+        for (int k = 0; k < 6; ++k) s[k] = state[(5 + k) * kBlock + so];
         const R rho = R(1) + dr, r2 = rho - r1;
         const R inv_rho = R(1) / rho;
         // Colour gradient from the phase field of planes d-1, d, d+1.
@@ -360,7 +365,8 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(const R *__restrict_
 // Second pass: the phase-field chain of the colour gradient.
 template <int Q, class R>
 __global__ __launch_bounds__(256) void k_cg_adjoint_phi(const R *__restrict__ state, const R *__restrict__ gG,
-                                                        R *__restrict__ lam_out, int nx, int ny, int nz, int64_t N)
+                                                        R *__restrict__ lam_out, int nx, int ny, int nz, int64_t N,
+                                                        MomentLayout lay)
 {
     using L = Lattice<Q>;
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -388,7 +394,8 @@ __global__ __launch_bounds__(256) void k_cg_adjoint_phi(const R *__restrict__ st
         if (cz) c = cz > 0 ? c + gG[2 * N + s] : c - gG[2 * N + s];
         gphi = fma_(w3, c, gphi);
     }
-    const R rho = R(1) + state[n], r1 = state[N + n], r2 = rho - r1;
+    const int64_t so = lay.node(x, y, z);
+    const R rho = R(1) + state[so], r1 = state[kBlock + so], r2 = rho - r1;
     const R k2 = R(2) * gphi / (rho * rho);
     lam_out[n] = fma_(k2, r2, lam_out[n]);
     lam_out[N + n] = fma_(-k2, r1, lam_out[N + n]);
@@ -417,6 +424,7 @@ hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *la
     g.ny = c->ny;
     g.nz = c->nz;
     g.N = c->N;
+    g.lay = c->lay;
     g.tiles_x = (c->nx + TX - 1) / TX;
     g.tiles_y = (c->ny + TY - 1) / TY;
     g.zchunk = choose_zchunk(c->nz, g.tiles_x * g.tiles_y, 256 * 2);
@@ -431,7 +439,7 @@ hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *la
     if (e != hipSuccess) return e;
     const unsigned nb = (unsigned)((c->N + 255) / 256);
     hipLaunchKernelGGL((k_cg_adjoint_phi<Q, R>), dim3(nb), dim3(256), 0, c->stream, static_cast<const R *>(state),
-                       static_cast<const R *>(gG), static_cast<R *>(lam_out), c->nx, c->ny, c->nz, c->N);
+                       static_cast<const R *>(gG), static_cast<R *>(lam_out), c->nx, c->ny, c->nz, c->N, c->lay);
     e = hipGetLastError();
     if (e != hipSuccess || !dtau) return e;
     hipLaunchKernelGGL(k_cg_add_partials, dim3(1), dim3(256), 0, c->stream, c->partials, (int)blocks, dtau);

@@ -46,6 +46,19 @@ __device__ __forceinline__ float sqrt_<float>(float x)
     return __builtin_sqrtf(x);
 }
 
+// 1/sqrt(x): FP32 uses the hardware reciprocal square root (about 1 ulp);
+// FP64 keeps the correctly rounded quotient.
+template <class R>
+__device__ __forceinline__ R rsqrt_(R x)
+{
+    return R(1) / sqrt_<R>(x);
+}
+template <>
+__device__ __forceinline__ float rsqrt_<float>(float x)
+{
+    return __builtin_amdgcn_rsqf(x);
+}
+
 template <class R>
 struct CgAcc {
     MomentAcc<R> m;
@@ -86,7 +99,7 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
     const int x0 = tx * TX, y0 = ty * TY;
     const int z0 = chunk * g.zchunk;
     const int z_end = min(z0 + g.zchunk, g.nz);
-    const int64_t plane = (int64_t)g.nx * g.ny;
+    const int64_t plane = g.lay.plane;  // stored elements per z-plane
 
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
@@ -119,12 +132,12 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
     }
     auto src_to_phi = [](int h) { return (h / SX + 1) * FX + (h % SX + 1); };
     auto xy_src = [&](int h) -> int64_t {
-        return (int64_t)wrap_coord(x0 - 1 + h % SX, g.nx) + (int64_t)g.nx * wrap_coord(y0 - 1 + h / SX, g.ny);
+        return g.lay.xy(wrap_coord(x0 - 1 + h % SX, g.nx), wrap_coord(y0 - 1 + h / SX, g.ny));
     };
     const int64_t own_xy = xy_src(h0);
     const int64_t ring_xy = has_ring ? xy_src(hr) : 0;
     const int64_t outer_xy =
-        has_outer ? (int64_t)wrap_coord(x0 - 2 + ko % FX, g.nx) + (int64_t)g.nx * wrap_coord(y0 - 2 + ko / FX, g.ny)
+        has_outer ? g.lay.xy(wrap_coord(x0 - 2 + ko % FX, g.nx), wrap_coord(y0 - 2 + ko / FX, g.ny))
                   : 0;
     const int k_own = src_to_phi(h0), k_ring = src_to_phi(hr);
 
@@ -137,11 +150,11 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
     auto zwrap = [&](int p) { return p < 0 ? p + g.nz : (p >= g.nz ? p - g.nz : p); };
     auto fetch = [&](int p, PlaneRegs &r) {
         const int64_t zo = (int64_t)zwrap(p) * plane;
-        load_moments<R, 11>(in, g.N, own_xy + zo, r.own);
-        if (has_ring) load_moments<R, 11>(in, g.N, ring_xy + zo, r.ring);
+        load_moments<R, 11>(in, kBlock, own_xy + zo, r.own);
+        if (has_ring) load_moments<R, 11>(in, kBlock, ring_xy + zo, r.ring);
         if (has_outer) {
             r.outer_dr = in[outer_xy + zo];
-            r.outer_r1 = in[g.N + outer_xy + zo];
+            r.outer_r1 = in[kBlock + outer_xy + zo];
         }
     };
     auto phi_of = [](R dr, R r1) { return fma_(R(2) * r1, reciprocal<R>(R(1) + dr), R(-1)); };
@@ -164,7 +177,9 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
         const R *phm = lds_phi + slot_of(p - 1) * FN;
         const R *ph0 = lds_phi + slot_of(p) * FN;
         const R *php = lds_phi + slot_of(p + 1) * FN;
-        R Gx = R(0), Gy = R(0), Gz = R(0);
+        // G = 3 sum_i w_i c_i phi(y + c_i): the signed phi values are summed
+        // per weight class (faces, edges, corners) and scaled once per class.
+        R gf[3] = {R(0), R(0), R(0)}, ge[3] = {R(0), R(0), R(0)}, gc[3] = {R(0), R(0), R(0)};
 #pragma unroll
         for (int cz = -1; cz <= 1; ++cz)
 #pragma unroll
@@ -173,13 +188,23 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
                 for (int cx = -1; cx <= 1; ++cx) {
                     if ((cx == 0 && cy == 0 && cz == 0) || !has_dir<Q>(cx, cy, cz)) continue;
                     const R *ph = cz < 0 ? phm : (cz == 0 ? ph0 : php);
-                    const R wphi = R(3.0 * weight<Q>(cx, cy, cz)) * ph[kc + cy * FX + cx];
-                    if (cx != 0) Gx = cx > 0 ? Gx + wphi : Gx - wphi;
-                    if (cy != 0) Gy = cy > 0 ? Gy + wphi : Gy - wphi;
-                    if (cz != 0) Gz = cz > 0 ? Gz + wphi : Gz - wphi;
+                    const R f = ph[kc + cy * FX + cx];
+                    const int cls = cx * cx + cy * cy + cz * cz;
+                    R *acc_c = cls == 1 ? gf : (cls == 2 ? ge : gc);
+                    if (cx != 0) acc_c[0] = cx > 0 ? acc_c[0] + f : acc_c[0] - f;
+                    if (cy != 0) acc_c[1] = cy > 0 ? acc_c[1] + f : acc_c[1] - f;
+                    if (cz != 0) acc_c[2] = cz > 0 ? acc_c[2] + f : acc_c[2] - f;
                 }
+        constexpr double w3f = 3.0 * weight<Q>(1, 0, 0), w3e = 3.0 * weight<Q>(1, 1, 0), w3c = 3.0 * weight<Q>(1, 1, 1);
+        R Gv[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Gv[a] = fma_(R(w3e), ge[a], R(w3f) * gf[a]);
+            if (Q == 27) Gv[a] = fma_(R(w3c), gc[a], Gv[a]);
+        }
+        const R Gx = Gv[0], Gy = Gv[1], Gz = Gv[2];
         const R G2 = fma_(Gx, Gx, fma_(Gy, Gy, Gz * Gz));
-        const R invD = R(1) / sqrt_<R>(G2 + R(kEpsG * kEpsG));
+        const R invD = rsqrt_<R>(G2 + R(kEpsG * kEpsG));
         const R nx = Gx * invD, ny = Gy * invD, nz = Gz * invD;
 
         const R dr = v.v[0], r1 = v.v[1];
@@ -206,6 +231,13 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
         // so that each node emits exactly its species-1 mass (the identity
         // sum_i f1_i = rho1 holds in exact arithmetic: the weights sum to one
         // and the recolouring terms cancel in +-c pairs).
+        // f1_i = (rho1/rho) (w_i + h~_i) + B w_i (c_i.n)/|c_i|, written as
+        // fma(B w_i/|c_i|, c_i.n, fma(rho1/rho, h~_i, (rho1/rho) w_i)) with the
+        // per-class products and the in-plane sums n_a +- n_b formed once.
+        constexpr double wf = weight<Q>(1, 0, 0), we = weight<Q>(1, 1, 0), wc = weight<Q>(1, 1, 1);
+        const R awf = a * R(wf), awe = a * R(we), awc = a * R(wc);
+        const R bwf = B * R(wf), bwe = B * R(we * inv_speed<Q>(1, 1, 0)), bwc = B * R(wc * inv_speed<Q>(1, 1, 1));
+        const R sxy = nx + ny, dxy = nx - ny, sxz = nx + nz, dxz = nx - nz, syz = ny + nz, dyz = ny - nz;
         R f1_moving = R(0);
 #pragma unroll
         for (int cz = -1; cz <= 1; ++cz)
@@ -214,12 +246,22 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
                 const int cx = sl % 3 - 1, cy = sl / 3 - 1;
                 if (!has_dir<Q>(cx, cy, cz) || (cx == 0 && cy == 0 && cz == 0)) continue;
                 const R hv = L[cz + 1].v[sl];
-                R cn = R(0);
-                if (cx != 0) cn = cx > 0 ? cn + nx : cn - nx;
-                if (cy != 0) cn = cy > 0 ? cn + ny : cn - ny;
-                if (cz != 0) cn = cz > 0 ? cn + nz : cn - nz;
-                const R f1 = fma_(B * R(weight<Q>(cx, cy, cz) * inv_speed<Q>(cx, cy, cz)), cn,
-                                  a * (R(weight<Q>(cx, cy, cz)) + hv));
+                const int cls = cx * cx + cy * cy + cz * cz;
+                R cn;
+                if (cls == 1) {
+                    cn = cx ? (cx > 0 ? nx : -nx) : cy ? (cy > 0 ? ny : -ny) : (cz > 0 ? nz : -nz);
+                } else if (cls == 2) {
+                    if (cz == 0) cn = cx == cy ? (cx > 0 ? sxy : -sxy) : (cx > 0 ? dxy : -dxy);
+                    else if (cy == 0) cn = cx == cz ? (cx > 0 ? sxz : -sxz) : (cx > 0 ? dxz : -dxz);
+                    else cn = cy == cz ? (cy > 0 ? syz : -syz) : (cy > 0 ? dyz : -dyz);
+                } else {
+                    const R t = cy == cx ? sxy : dxy;  // cx nx + cy ny, up to the sign of cx
+                    const R txy = cx > 0 ? t : -t;
+                    cn = cz > 0 ? txy + nz : txy - nz;
+                }
+                const R aw = cls == 1 ? awf : (cls == 2 ? awe : awc);
+                const R bw = cls == 1 ? bwf : (cls == 2 ? bwe : bwc);
+                const R f1 = fma_(bw, cn, fma_(a, hv, aw));
                 f1_moving += f1;
                 const int s = lds_slot<Q>(cz, sl);
                 if (s >= 0) {
@@ -269,20 +311,20 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
 
         const int d = p - 1;
         if (d >= z0 && active) {
-            const int64_t o = (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)d * plane;
+            const int64_t o = g.lay.xy(x0 + lx, y0 + ly) + (int64_t)d * plane;
             const MomentAcc<R> &a = acc[0].m;
             const R m3 = R(-1.0 / 3.0);
             store_out(out + o, a.r);
-            store_out(out + g.N + o, acc[0].rho1);
-            store_out(out + 2 * g.N + o, a.jx);
-            store_out(out + 3 * g.N + o, a.jy);
-            store_out(out + 4 * g.N + o, a.jz);
-            store_out(out + 5 * g.N + o, fma_(m3, a.r, a.mxx));
-            store_out(out + 6 * g.N + o, fma_(m3, a.r, a.myy));
-            store_out(out + 7 * g.N + o, fma_(m3, a.r, a.mzz));
-            store_out(out + 8 * g.N + o, a.mxy);
-            store_out(out + 9 * g.N + o, a.mxz);
-            store_out(out + 10 * g.N + o, a.myz);
+            store_out(out + kBlock + o, acc[0].rho1);
+            store_out(out + 2 * kBlock + o, a.jx);
+            store_out(out + 3 * kBlock + o, a.jy);
+            store_out(out + 4 * kBlock + o, a.jz);
+            store_out(out + 5 * kBlock + o, fma_(m3, a.r, a.mxx));
+            store_out(out + 6 * kBlock + o, fma_(m3, a.r, a.myy));
+            store_out(out + 7 * kBlock + o, fma_(m3, a.r, a.mzz));
+            store_out(out + 8 * kBlock + o, a.mxy);
+            store_out(out + 9 * kBlock + o, a.mxz);
+            store_out(out + 10 * kBlock + o, a.myz);
         }
         acc[0] = acc[1];
         acc[1] = acc[2];
@@ -309,6 +351,7 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out)
     g.ny = c->ny;
     g.nz = c->nz;
     g.N = c->N;
+    g.lay = c->lay;
     g.tiles_x = (c->nx + TX - 1) / TX;
     g.tiles_y = (c->ny + TY - 1) / TY;
     g.zchunk = choose_zchunk(c->nz, g.tiles_x * g.tiles_y, 256 * WG_PER_CU);

@@ -22,12 +22,21 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / k
 
 // ---- moment scheme -------------------------------------------------------------
 
+// Stored offset of public node n (x fastest) in the blocked moment layout.
+__device__ __forceinline__ int64_t stored_node(const MomentLayout &L, int64_t n, int nx, int ny)
+{
+    const int x = (int)(n % nx);
+    const int64_t t = n / nx;
+    return L.node(x, (int)(t % ny), (int)(t / ny));
+}
+
 template <class S, class T>
-__global__ void k_set_moment_state(const T *__restrict__ src, int64_t stride, S *__restrict__ st, int64_t N,
-                                   int species, double s_pi)
+__global__ void k_set_moment_state(const T *__restrict__ src, int64_t stride, S *__restrict__ st, int64_t N, int nx,
+                                   int ny, MomentLayout lay, int species, double s_pi)
 {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
+    const int64_t so = stored_node(lay, n, nx, ny);
     double rho, rho1 = 0.0;
     int off;
     if (species == 1) {
@@ -39,38 +48,39 @@ __global__ void k_set_moment_state(const T *__restrict__ src, int64_t stride, S 
         off = 2;
     }
     const int js = species == 1 ? 1 : 2;  // first stored j field
-    st[n] = Store<S>::make((typename Store<S>::real)(rho - 1.0));
-    if (species == 2) st[N + n] = Store<S>::make((typename Store<S>::real)rho1);
+    st[so] = Store<S>::make((typename Store<S>::real)(rho - 1.0));
+    if (species == 2) st[kBlock + so] = Store<S>::make((typename Store<S>::real)rho1);
     for (int a = 0; a < 3; ++a)
-        st[(js + a) * N + n] = Store<S>::make((typename Store<S>::real)src[(off + a) * stride + n]);
+        st[(js + a) * kBlock + so] = Store<S>::make((typename Store<S>::real)src[(off + a) * stride + n]);
     for (int k = 0; k < 6; ++k) {
         double p = (double)src[(off + 3 + k) * stride + n];
         if (k < 3) p -= rho / 3.0;
-        st[(js + 3 + k) * N + n] = Store<S>::make((typename Store<S>::real)(p * s_pi));
+        st[(js + 3 + k) * kBlock + so] = Store<S>::make((typename Store<S>::real)(p * s_pi));
     }
 }
 
 template <class S, class T>
-__global__ void k_get_moment_state(const S *__restrict__ st, T *__restrict__ dst, int64_t stride, int64_t N,
-                                   int species, double inv_s_pi)
+__global__ void k_get_moment_state(const S *__restrict__ st, T *__restrict__ dst, int64_t stride, int64_t N, int nx,
+                                   int ny, MomentLayout lay, int species, double inv_s_pi)
 {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
-    const double rho = 1.0 + (double)Store<S>::load(st[n]);
+    const int64_t so = stored_node(lay, n, nx, ny);
+    const double rho = 1.0 + (double)Store<S>::load(st[so]);
     const int js = species == 1 ? 1 : 2;
     int off;
     if (species == 1) {
         dst[n] = (T)rho;
         off = 1;
     } else {
-        const double rho1 = (double)Store<S>::load(st[N + n]);
+        const double rho1 = (double)Store<S>::load(st[kBlock + so]);
         dst[n] = (T)rho1;
         dst[stride + n] = (T)(rho - rho1);
         off = 2;
     }
-    for (int a = 0; a < 3; ++a) dst[(off + a) * stride + n] = (T)(double)Store<S>::load(st[(js + a) * N + n]);
+    for (int a = 0; a < 3; ++a) dst[(off + a) * stride + n] = (T)(double)Store<S>::load(st[(js + a) * kBlock + so]);
     for (int k = 0; k < 6; ++k) {
-        double p = (double)Store<S>::load(st[(js + 3 + k) * N + n]) * inv_s_pi;
+        double p = (double)Store<S>::load(st[(js + 3 + k) * kBlock + so]) * inv_s_pi;
         if (k < 3) p += rho / 3.0;
         dst[(off + 3 + k) * stride + n] = (T)p;
     }
@@ -256,19 +266,21 @@ __device__ void block_sum5(double v[5], double *out)
 }
 
 template <class S>
-__global__ __launch_bounds__(kThreads) void k_reduce_moment(const S *__restrict__ st, int64_t N, int species,
+__global__ __launch_bounds__(kThreads) void k_reduce_moment(const S *__restrict__ st, int64_t N, int nx, int ny,
+                                                            MomentLayout lay, int species,
                                                             double *__restrict__ partials)
 {
     double v[5] = {0, 0, 0, 0, 0};
     const int js = species == 1 ? 1 : 2;
     for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < N; n += (int64_t)gridDim.x * kThreads) {
+        const int64_t so = stored_node(lay, n, nx, ny);
         if (species == 1) {
-            v[0] += (double)Store<S>::load(st[n]);
+            v[0] += (double)Store<S>::load(st[so]);
         } else {
-            v[0] += (double)Store<S>::load(st[N + n]);
-            v[1] += (double)Store<S>::load(st[n]);
+            v[0] += (double)Store<S>::load(st[kBlock + so]);
+            v[1] += (double)Store<S>::load(st[so]);
         }
-        for (int a = 0; a < 3; ++a) v[2 + a] += (double)Store<S>::load(st[(js + a) * N + n]);
+        for (int a = 0; a < 3; ++a) v[2 + a] += (double)Store<S>::load(st[(js + a) * kBlock + so]);
     }
     block_sum5(v, partials + 5 * blockIdx.x);
 }
@@ -347,7 +359,8 @@ hipError_t launch_set_moments(const lbm_ctx *c, const void *src, int64_t stride,
             const T *s = static_cast<const T *>(src);
             if (c->scheme == LBM_SCHEME_MOMENT) {
                 hipLaunchKernelGGL((k_set_moment_state<S, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
-                                   s, stride, static_cast<S *>(state), c->N, c->species, c->s_pi);
+                                   s, stride, static_cast<S *>(state), c->N, c->nx, c->ny, c->lay, c->species,
+                                   c->s_pi);
             } else if (c->species == 2) {
                 if (c->q == 19)
                     hipLaunchKernelGGL((k_set_population2_state<19, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0,
@@ -378,7 +391,7 @@ hipError_t launch_get_moments(const lbm_ctx *c, const void *state, void *dst, in
             const S *st = static_cast<const S *>(state);
             if (c->scheme == LBM_SCHEME_MOMENT) {
                 hipLaunchKernelGGL((k_get_moment_state<S, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
-                                   st, d, stride, c->N, c->species, 1.0 / c->s_pi);
+                                   st, d, stride, c->N, c->nx, c->ny, c->lay, c->species, 1.0 / c->s_pi);
             } else if (c->species == 2) {
                 const float *A = reinterpret_cast<const float *>(state);
                 if (c->q == 19)
@@ -425,7 +438,7 @@ hipError_t launch_reduce(const lbm_ctx *c, const void *state)
         const S *st = static_cast<const S *>(state);
         if (c->scheme == LBM_SCHEME_MOMENT)
             hipLaunchKernelGGL((k_reduce_moment<S>), dim3(kReduceBlocks), dim3(kThreads), 0, c->stream, st, c->N,
-                               c->species, c->partials);
+                               c->nx, c->ny, c->lay, c->species, c->partials);
         else if (c->species == 2 && c->q == 19)
             hipLaunchKernelGGL((k_reduce_population2<19>), dim3(kReduceBlocks), dim3(kThreads), 0, c->stream,
                                reinterpret_cast<const float *>(state), c->N, c->partials);

@@ -6,6 +6,7 @@
 
 #include <string>
 
+#include "layout.hpp"
 #include "lbm.h"
 
 struct lbm_ctx {
@@ -18,6 +19,8 @@ struct lbm_ctx {
     int check_every = 0;
     int nfields = 0;  // stored arrays per state copy
     size_t elem = 4;  // bytes per stored element
+    int64_t state_elems = 0;  // elements per state copy (blocked moment layout or q x N populations)
+    lbm::MomentLayout lay{};  // stored layout of the moment scheme
     void *state[2] = {nullptr, nullptr};
     int cur = 0;      // state[cur] holds the current time level
     double *partials = nullptr;  // FP64 reduction partials (kReduceBlocks x 5)

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
     const int x0 = tx * TX, y0 = ty * TY;
     const int z0 = chunk * g.zchunk;
     const int z_end = min(z0 + g.zchunk, g.nz);
-    const int64_t plane = (int64_t)g.nx * g.ny;
+    const int64_t plane = g.lay.plane;  // stored elements per z-plane
 
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
     }
     auto wrap_xy = [&](int h) -> int64_t {
         const int hx = h % HX, hy = h / HX;
-        return (int64_t)wrap_coord(x0 - 1 + hx, g.nx) + (int64_t)g.nx * wrap_coord(y0 - 1 + hy, g.ny);
+        return g.lay.xy(wrap_coord(x0 - 1 + hx, g.nx), wrap_coord(y0 - 1 + hy, g.ny));
     };
     const int64_t own_xy = wrap_xy(h0);
     const int64_t ring_xy = has_ring ? wrap_xy(hr) : 0;
@@ -93,8 +93,8 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
     Moments<R> own_a, own_b, ring_a, ring_b;
     auto fetch = [&](int p, Moments<R> &own, Moments<R> &ring) {
         const int zs = p < 0 ? p + g.nz : (p >= g.nz ? p - g.nz : p);
-        load_moments<S>(in, g.N, own_xy + (int64_t)zs * plane, own);
-        if (has_ring) load_moments<S>(in, g.N, ring_xy + (int64_t)zs * plane, ring);
+        load_moments<S>(in, kBlock, own_xy + (int64_t)zs * plane, own);
+        if (has_ring) load_moments<S>(in, kBlock, ring_xy + (int64_t)zs * plane, ring);
     };
 
     auto collide_node = [&](const Moments<R> &v) {
@@ -153,20 +153,20 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
         // Plane p-1 has now received from p-2, p-1 and p.
         const int d = p - 1;
         if (d >= z0 && active) {
-            const int64_t o = (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)d * plane;
+            const int64_t o = g.lay.xy(x0 + lx, y0 + ly) + (int64_t)d * plane;
             const MomentAcc<R> &a = acc[0];
             const R m3 = R(-1.0 / 3.0);
             const R sc = kScaled ? s_pi : R(1);
             store_out(out + o, Store<S>::make(a.r));
-            store_out(out + g.N + o, Store<S>::make(a.jx));
-            store_out(out + 2 * g.N + o, Store<S>::make(a.jy));
-            store_out(out + 3 * g.N + o, Store<S>::make(a.jz));
-            store_out(out + 4 * g.N + o, Store<S>::make(kScaled ? fma_(m3, a.r, a.mxx) * sc : fma_(m3, a.r, a.mxx)));
-            store_out(out + 5 * g.N + o, Store<S>::make(kScaled ? fma_(m3, a.r, a.myy) * sc : fma_(m3, a.r, a.myy)));
-            store_out(out + 6 * g.N + o, Store<S>::make(kScaled ? fma_(m3, a.r, a.mzz) * sc : fma_(m3, a.r, a.mzz)));
-            store_out(out + 7 * g.N + o, Store<S>::make(kScaled ? a.mxy * sc : a.mxy));
-            store_out(out + 8 * g.N + o, Store<S>::make(kScaled ? a.mxz * sc : a.mxz));
-            store_out(out + 9 * g.N + o, Store<S>::make(kScaled ? a.myz * sc : a.myz));
+            store_out(out + kBlock + o, Store<S>::make(a.jx));
+            store_out(out + 2 * kBlock + o, Store<S>::make(a.jy));
+            store_out(out + 3 * kBlock + o, Store<S>::make(a.jz));
+            store_out(out + 4 * kBlock + o, Store<S>::make(kScaled ? fma_(m3, a.r, a.mxx) * sc : fma_(m3, a.r, a.mxx)));
+            store_out(out + 5 * kBlock + o, Store<S>::make(kScaled ? fma_(m3, a.r, a.myy) * sc : fma_(m3, a.r, a.myy)));
+            store_out(out + 6 * kBlock + o, Store<S>::make(kScaled ? fma_(m3, a.r, a.mzz) * sc : fma_(m3, a.r, a.mzz)));
+            store_out(out + 7 * kBlock + o, Store<S>::make(kScaled ? a.mxy * sc : a.mxy));
+            store_out(out + 8 * kBlock + o, Store<S>::make(kScaled ? a.mxz * sc : a.mxz));
+            store_out(out + 9 * kBlock + o, Store<S>::make(kScaled ? a.myz * sc : a.myz));
         }
         acc[0] = acc[1];
         acc[1] = acc[2];
@@ -190,6 +190,7 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out)
     g.ny = c->ny;
     g.nz = c->nz;
     g.N = c->N;
+    g.lay = c->lay;
     g.tiles_x = (c->nx + TX - 1) / TX;
     g.tiles_y = (c->ny + TY - 1) / TY;
     g.zchunk = choose_zchunk(c->nz, g.tiles_x * g.tiles_y, 256 * WG_PER_CU);

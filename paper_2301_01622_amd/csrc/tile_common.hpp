@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "layout.hpp"
 #include "moment_math.hpp"
 #include "storage.hpp"
 
@@ -16,9 +17,12 @@ struct TileGrid {
     int nx, ny, nz;
     int64_t N;
     int tiles_x, tiles_y, chunks, zchunk;
+    MomentLayout lay;  // stored layout of the moment state
 };
 
 // Moments of one source node, already unpacked to the arithmetic type.
+// load_moments reads field k at in[k * stride + idx] (stride kBlock for the
+// stored moment state, N for arrays in the public layout).
 template <class R, int NF = 10>
 struct Moments {
     R v[NF];
