@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS + % HBM roofline, moment-LB vs population-LB on 1 MI355X; adjoint/forward cost"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "moment_step_256cube_d3q27_f32_traffic.json")
-KERNEL_SOURCES = ["moment_step.hip", "moment_math.hpp", "lattice.hpp", "storage.hpp"]
+KERNEL_SOURCES = ["moment_step.hip", "moment_math.hpp", "lattice.hpp", "storage.hpp", "tile_common.hpp", "layout.hpp"]
 
 
 def kernel_hash() -> str:
