@@ -362,43 +362,112 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(const R *__restrict_
     if (tid == 0) partials[blockIdx.x] = red[0];
 }
 
-// Second pass: the phase-field chain of the colour gradient.
-template <int Q, class R>
-__global__ __launch_bounds__(256) void k_cg_adjoint_phi(const R *__restrict__ state, const R *__restrict__ gG,
-                                                        R *__restrict__ lam_out, int nx, int ny, int nz, int64_t N,
-                                                        MomentLayout lay)
+// Second pass: the phase-field chain of the colour gradient,
+//   gphi(z) = sum_k 3 w_k c_k . gG(z - c_k),
+//   lam1 += gphi 2 rho2/rho^2,  lam2 -= gphi 2 rho1/rho^2.
+// A workgroup marches a TX x TY tile along z; the three components of gG for
+// the tile plus a one-node halo ring are kept for planes z-1, z, z+1 in an LDS
+// ring, so each gG value is read from HBM about once (a one-thread-per-node
+// stencil re-reads the neighbouring planes from memory).
+template <int Q, class R, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_cg_adjoint_phi(const R *__restrict__ state, const R *__restrict__ gG,
+                                                           R *__restrict__ lam_out, TileGrid g)
 {
     using L = Lattice<Q>;
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    const int x = (int)(n % nx);
-    const int64_t t = n / nx;
-    const int y = (int)(t % ny), z = (int)(t / ny);
-    R gphi = R(0);
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-        const int cx = L::cx(k), cy = L::cy(k), cz = L::cz(k);
-        if (!cx && !cy && !cz) continue;
-        int xs = x - cx, ys = y - cy, zs = z - cz;  // G(z - c_k) read phi(z)
-        xs += xs < 0 ? nx : 0;
-        xs -= xs >= nx ? nx : 0;
-        ys += ys < 0 ? ny : 0;
-        ys -= ys >= ny ? ny : 0;
-        zs += zs < 0 ? nz : 0;
-        zs -= zs >= nz ? nz : 0;
-        const int64_t s = (int64_t)xs + (int64_t)nx * ((int64_t)ys + (int64_t)ny * zs);
-        const R w3 = R(3.0 * L::w(k));
-        R c = R(0);
-        if (cx) c = cx > 0 ? c + gG[s] : c - gG[s];
-        if (cy) c = cy > 0 ? c + gG[N + s] : c - gG[N + s];
-        if (cz) c = cz > 0 ? c + gG[2 * N + s] : c - gG[2 * N + s];
-        gphi = fma_(w3, c, gphi);
+    constexpr int NT = TX * TY;
+    constexpr int HX = TX + 2, HY = TY + 2, HN = HX * HY;
+    constexpr int RING = HN - NT;
+    static_assert(RING <= NT, "halo ring must fit one pass");
+    __shared__ R lds_g[3 * 3 * HN];  // [plane slot][component][halo tile]
+
+    const int b = xcd_tile_id();
+    const int tx = b % g.tiles_x;
+    const int ty = (b / g.tiles_x) % g.tiles_y;
+    const int chunk = b / (g.tiles_x * g.tiles_y);
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int z0 = chunk * g.zchunk;
+    const int z_end = min(z0 + g.zchunk, g.nz);
+    const int64_t plane = (int64_t)g.nx * g.ny;
+
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly = tid / TX;
+    const bool active = (x0 + lx < g.nx) && (y0 + ly < g.ny);
+    const int h0 = (ly + 1) * HX + (lx + 1);
+    const bool has_ring = tid < RING;
+    int hr;
+    {
+        const int m = tid;
+        int hx, hy;
+        if (m < HX) { hx = m; hy = 0; }
+        else if (m < 2 * HX) { hx = m - HX; hy = HY - 1; }
+        else if (m < 2 * HX + TY) { hx = 0; hy = 1 + (m - 2 * HX); }
+        else { hx = HX - 1; hy = 1 + (m - 2 * HX - TY); }
+        hr = hy * HX + hx;
     }
-    const int64_t so = lay.node(x, y, z);
-    const R rho = R(1) + state[so], r1 = state[kBlock + so], r2 = rho - r1;
-    const R k2 = R(2) * gphi / (rho * rho);
-    lam_out[n] = fma_(k2, r2, lam_out[n]);
-    lam_out[N + n] = fma_(-k2, r1, lam_out[N + n]);
+    auto xy_of = [&](int h) -> int64_t {
+        return (int64_t)wrap_coord(x0 - 1 + h % HX, g.nx) + (int64_t)g.nx * wrap_coord(y0 - 1 + h / HX, g.ny);
+    };
+    const int64_t own_xy = xy_of(h0);
+    const int64_t ring_xy = has_ring ? xy_of(hr) : 0;
+    auto zs_of = [&](int p) { return p < 0 ? p + g.nz : (p >= g.nz ? p - g.nz : p); };
+    auto slot = [&](int p) { return (p - z0 + 3) % 3; };
+
+    R go[3], gr[3];
+    auto fetch = [&](int p) {
+        const int64_t zo = (int64_t)zs_of(p) * plane;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) go[a] = gG[a * g.N + own_xy + zo];
+        if (has_ring) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gr[a] = gG[a * g.N + ring_xy + zo];
+        }
+    };
+    auto publish = [&](int p) {
+        R *d = lds_g + slot(p) * 3 * HN;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) d[a * HN + h0] = go[a];
+        if (has_ring) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) d[a * HN + hr] = gr[a];
+        }
+    };
+
+    // Planes z0-1 and z0 are in LDS and plane z0+1 in registers before the
+    // loop; each step publishes plane p+1, then loads plane p+2 while plane p
+    // is computed.  Slot (p+1) mod 3 held plane p-2, last read before the
+    // previous step's closing barrier.
+    fetch(z0 - 1);
+    publish(z0 - 1);
+    fetch(z0);
+    publish(z0);
+    fetch(z0 + 1);
+    for (int p = z0; p < z_end; ++p) {
+        publish(p + 1);
+        __syncthreads();
+        fetch(p + 2);
+        if (active) {
+            R gphi = R(0);
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                const int cx = L::cx(k), cy = L::cy(k), cz = L::cz(k);
+                if (!cx && !cy && !cz) continue;
+                const R *d = lds_g + slot(p - cz) * 3 * HN;
+                const int h = h0 - cy * HX - cx;
+                R c = R(0);
+                if (cx) c = cx > 0 ? c + d[h] : c - d[h];
+                if (cy) c = cy > 0 ? c + d[HN + h] : c - d[HN + h];
+                if (cz) c = cz > 0 ? c + d[2 * HN + h] : c - d[2 * HN + h];
+                gphi = fma_(R(3.0 * L::w(k)), c, gphi);
+            }
+            const int64_t n = (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)p * plane;
+            const int64_t so = g.lay.xy(x0 + lx, y0 + ly) + (int64_t)p * g.lay.plane;
+            const R rho = R(1) + state[so], r1 = state[kBlock + so], r2 = rho - r1;
+            const R k2 = R(2) * gphi / (rho * rho);
+            lam_out[n] = fma_(k2, r2, lam_out[n]);
+            lam_out[g.N + n] = fma_(-k2, r1, lam_out[g.N + n]);
+        }
+        __syncthreads();
+    }
 }
 
 __global__ __launch_bounds__(256) void k_cg_add_partials(const double *__restrict__ partials, int n,
@@ -437,9 +506,15 @@ hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *la
                        g, (R)c->omega, (R)(c->A / 9.0), (R)c->beta, c->tau, c->partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned nb = (unsigned)((c->N + 255) / 256);
-    hipLaunchKernelGGL((k_cg_adjoint_phi<Q, R>), dim3(nb), dim3(256), 0, c->stream, static_cast<const R *>(state),
-                       static_cast<const R *>(gG), static_cast<R *>(lam_out), c->nx, c->ny, c->nz, c->N, c->lay);
+    TileGrid gp = g;
+    gp.tiles_x = (c->nx + 63) / 64;
+    gp.tiles_y = (c->ny + 15) / 16;
+    gp.zchunk = choose_zchunk(c->nz, gp.tiles_x * gp.tiles_y, 256);
+    gp.chunks = (c->nz + gp.zchunk - 1) / gp.zchunk;
+    const int64_t pblocks = (int64_t)gp.tiles_x * gp.tiles_y * gp.chunks;
+    if (pblocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_cg_adjoint_phi<Q, R, 64, 16>), dim3((unsigned)pblocks), dim3(1024), 0, c->stream,
+                       static_cast<const R *>(state), static_cast<const R *>(gG), static_cast<R *>(lam_out), gp);
     e = hipGetLastError();
     if (e != hipSuccess || !dtau) return e;
     hipLaunchKernelGGL(k_cg_add_partials, dim3(1), dim3(256), 0, c->stream, c->partials, (int)blocks, dtau);

@@ -366,10 +366,15 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out)
 
 } // namespace
 
+// D3Q19 FP32 tiles: 64 x 4 nodes (full 64-wide rows of the stored blocks),
+// z-chunks sized for two resident workgroups per CU (on 512 x 256 x 256 each
+// workgroup marches the whole column).  Measured against 32 x 8, 64 x 8,
+// 32 x 16 and 128 x 4 tiles and other chunkings; the shape is a compile-time
+// choice (LBM_CG_TX, LBM_CG_TY, LBM_CG_WG).
 #ifndef LBM_CG_TX
-#define LBM_CG_TX 32
-#define LBM_CG_TY 8
-#define LBM_CG_WG 3
+#define LBM_CG_TX 64
+#define LBM_CG_TY 4
+#define LBM_CG_WG 2
 #endif
 
 hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out)
