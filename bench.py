@@ -73,7 +73,8 @@ def cpu_baseline(n: int, q: int, tau: float, steps: int, rho, u):
         "unit": "MLUPS",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"{steps} full time steps of the same {n}^3 D3Q27 box (FP64 C oracle, OpenMP, {threads} threads)",
+        "sample": f"{steps} full time steps of the same {n}^3 D3Q{q} box (FP64 C oracle, OpenMP, {threads} threads, "
+                  f"{dt:.1f} s)",
     }
 
 
@@ -177,7 +178,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-population", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-two-component", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=10,
                     help="also time this many state copies (plain copy kernel of known size)")
