@@ -57,3 +57,49 @@ def test_reduced_precision_storage_error(reference, storage):
     umax = np.abs(ur).max()
     assert report["max_abs_err"]["u"] <= 16 * eps * umax * np.sqrt(T)
     assert report["max_abs_err"]["rho"] <= 16 * eps * 3 * umax * np.sqrt(T)
+
+
+def test_full_size_reduced_precision_report():
+    """The configuration at full size: 512^3 D3Q27, tau = 0.55, 2000 steps,
+    u_x = 0.01 sin(2 pi y / 512) plus solenoidal noise of max norm 1e-4 (seed
+    16220004).  FP32, FP16 and BF16 storage against the FP64-storage run of
+    the same kernel: the FP64 path matches the FP64 oracle to 1e-12 on smaller
+    boxes, and the oracle itself would need hours for this one.  Per-field
+    errors are printed and bounded as above."""
+    from paper_2301_01622_amd.lbm import LBM
+    n, T, tau = 512, 2000, 0.55
+    print(f"[gpu] 512^3 D3Q27 storage report, {T} steps", flush=True)
+    rho, u = I.shear_wave_with_noise(n, seed=I.SEED_C4, u0=0.01, noise=1e-4)
+    rho_d, u_d = torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda()
+    del rho, u
+
+    def run(storage):
+        sim = LBM((n, n, n), 27, tau, storage=storage)
+        sim.set_equilibrium(rho_d, u_d)
+        sim.step(T)
+        out = sim.get_moments(torch.float64)
+        sim.close()
+        return out
+
+    ref = run("f64")
+    ur = ref[1:4] / ref[0]
+    umax = float(ur.abs().max())
+    for storage in ("f32", "f16", "bf16"):
+        got = run(storage)
+        assert bool(torch.isfinite(got).all())
+        ug = got[1:4] / got[0]
+        report = {
+            "storage": storage,
+            "max_abs_err": {
+                "rho": float((got[0] - ref[0]).abs().max()),
+                "u": float((ug - ur).abs().max()),
+                "P": float((got[4:] - ref[4:]).abs().max()),
+            },
+            "rel_l2_err_u": float(torch.sqrt(((ug - ur) ** 2).sum() / (ur ** 2).sum())),
+        }
+        print(f"[gpu] 512^3 storage error report {json.dumps(report)}", flush=True)
+        eps = 2.0 ** -(MANTISSA[storage] + 1)
+        assert report["max_abs_err"]["u"] <= 16 * eps * umax * np.sqrt(T)
+        assert report["max_abs_err"]["rho"] <= 16 * eps * 3 * umax * np.sqrt(T)
+        del got, ug
+        torch.cuda.empty_cache()
