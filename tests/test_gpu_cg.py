@@ -208,3 +208,67 @@ def test_population_colour_gradient_matches_oracle(LBM, oracle, q):
     _say(f"  max err per field {err}")
     assert err.max() <= 5e-6
     assert np.abs(t1[:2] - t0[:2]).max() <= 1e-4
+
+
+def test_full_size_droplet_collision_5000_steps():
+    """The droplet-collision configuration at full size and length
+    (512 x 256 x 256, D3Q19, R = 40, u = +-0.05, offset 0.5 R, 5000 steps; the
+    drops meet after about 800 steps and coalesce).  The FP32 run is compared
+    with the FP64-storage run of the same kernel (which matches the oracle to
+    1e-12 over hundreds of steps on smaller boxes; the oracle would need hours
+    here) through the observables of the configuration: the drop-averaged
+    density <rho1>_{rho1 > 0.5}, the x-centroids of rho1 in the two halves and
+    the kinetic energy.  Node-wise differences are reported; the merging film
+    amplifies rounding, so the bounds are ten times the spread of the FP64
+    run itself under a 1e-9 perturbation of rho1, and at least the bounds of
+    the configuration (centroids 0.05, <rho1> 1e-4 relative)."""
+    from paper_2301_01622_amd.lbm import LBM
+    shape, T = (256, 256, 512), 5000
+    print(f"[gpu] 512x256x256 droplet collision, {T} steps (FP64, FP64 perturbed, FP32)", flush=True)
+    r1, r2, u = I.droplet_collision_512(shape)
+    R12 = torch.from_numpy(np.stack([r1, r2])).cuda()
+    U = torch.from_numpy(u).cuda()
+    noise = 1e-9 * torch.from_numpy(np.random.default_rng(17).standard_normal(shape)).cuda()
+    xg = torch.arange(512, dtype=torch.float64, device="cuda").view(1, 1, 512).expand(*shape)
+    left = xg < 256
+
+    def observables(M):
+        r1 = M[0]
+        m = r1 > 0.5
+        cents = [float((r1 * xg * h).sum() / (r1 * h).sum()) for h in (left.double(), (~left).double())]
+        ke = float(0.5 * ((M[2:5] ** 2).sum(0) / (M[0] + M[1])).sum())
+        return float(r1[m].mean()), cents, ke
+
+    def run(storage, perturb=False):
+        sim = LBM((512, 256, 256), 19, TAU, species=2, storage=storage, sigma=SIGMA, beta=BETA)
+        rr = R12.clone()
+        if perturb:
+            rr[0] += noise
+            rr[1] -= noise
+        sim.set_equilibrium(rr, U)
+        sim.step(T)
+        out = sim.get_moments(torch.float64)
+        sim.close()
+        return out
+
+    ref = run("f64")
+    o_ref = observables(ref)
+    pert = run("f64", perturb=True)
+    o_pert = observables(pert)
+    spread_nodes = float((pert[0] - ref[0]).abs().max())
+    del pert
+    got = run("f32")
+    o_got = observables(got)
+    du = float((got[2:5] / (got[0] + got[1]) - ref[2:5] / (ref[0] + ref[1])).abs().max())
+    dr1 = float((got[0] - ref[0]).abs().max())
+    print(f"[gpu]   FP64: <rho1> {o_ref[0]:.8f} centroids {o_ref[1]} KE {o_ref[2]:.6e}", flush=True)
+    print(f"[gpu]   FP64 perturbed: <rho1> {o_pert[0]:.8f} centroids {o_pert[1]} KE {o_pert[2]:.6e}; "
+          f"max|d rho1| {spread_nodes:.2e}", flush=True)
+    print(f"[gpu]   FP32: <rho1> {o_got[0]:.8f} centroids {o_got[1]} KE {o_got[2]:.6e}; max|d rho1| {dr1:.2e}, "
+          f"max|du| {du:.2e}", flush=True)
+    s_rho = abs(o_pert[0] / o_ref[0] - 1)
+    s_c = max(abs(o_pert[1][0] - o_ref[1][0]), abs(o_pert[1][1] - o_ref[1][1]))
+    s_ke = abs(o_pert[2] / o_ref[2] - 1)
+    assert abs(o_got[0] / o_ref[0] - 1) <= max(10 * s_rho, 1e-4)
+    assert max(abs(o_got[1][0] - o_ref[1][0]), abs(o_got[1][1] - o_ref[1][1])) <= max(10 * s_c, 0.05)
+    assert abs(o_got[2] / o_ref[2] - 1) <= max(10 * s_ke, 1e-4)
