@@ -90,17 +90,19 @@ def adjoint_cost(sim, stream, steps: int, fwd_ms: float, algo_bytes: int = 120,
     sim.save_state(st)
     g = torch.Generator(device="cuda")
     g.manual_seed(7)
-    lam = torch.randn((sim.nfields,) + sim.shape, generator=g, device="cuda", dtype=sim.real_dtype)
-    lam_b = torch.empty_like(lam)
+    pub = torch.randn((sim.nfields,) + sim.shape, generator=g, device="cuda", dtype=sim.real_dtype)
+    # the rollout's path: co-states in the library's stored layout
+    lam, lam_b = sim.new_costate(), sim.new_costate()
+    sim.costate_to_stored(pub, lam)
     dtau = torch.zeros(1, dtype=torch.float64, device="cuda")
     for _ in range(3):
-        sim.adjoint_step(st, lam, lam_b, dtau)
+        sim.adjoint_step_stored(st, lam, lam_b, dtau)
         sim.step_state(st, slot)
     torch.cuda.synchronize()
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     e[0].record(stream)
     for _ in range(steps):
-        sim.adjoint_step(st, lam, lam_b, dtau)
+        sim.adjoint_step_stored(st, lam, lam_b, dtau)
     e[1].record(stream)
     for _ in range(steps):
         sim.step_state(st, slot)

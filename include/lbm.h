@@ -209,6 +209,29 @@ int lbm_step_state(lbm_ctx *ctx, const void *src_state, void *dst_state);
  * species with FP16/BF16 storage), LBM_ENOMEM, LBM_EDEVICE. */
 int lbm_adjoint_step(lbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out, double *dtau_accum);
 
+/* The same reverse step with both co-states in the stored (blocked) layout
+ * of the state instead of the public one: lam_next and lam_out are device
+ * buffers of lbm_costate_bytes() bytes (real type as for lbm_adjoint_step).
+ * A checkpointed rollout keeps its co-state in this layout between steps and
+ * converts it only at the ends (lbm_costate_to_stored / _from_stored); the
+ * results equal those of lbm_adjoint_step bit for bit.  Slots of the layout
+ * that belong to no node are neither read nor written.  Errors as for
+ * lbm_adjoint_step. */
+int lbm_adjoint_step_stored(lbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out,
+                            double *dtau_accum);
+
+/* Size in bytes of one co-state in the stored layout (moment scheme).
+ * Errors: LBM_EINVAL, LBM_ESTATE (population scheme). */
+int lbm_costate_bytes(const lbm_ctx *ctx, int64_t *bytes);
+
+/* Co-state conversion between the public layout (nfields arrays of N reals,
+ * x fastest) and the stored layout (lbm_costate_bytes() bytes); both device
+ * buffers, must not overlap.  Asynchronous on the context's stream.
+ * Errors: LBM_EINVAL (NULL or aliased), LBM_ESTATE (population scheme),
+ * LBM_EDEVICE. */
+int lbm_costate_to_stored(lbm_ctx *ctx, const void *public_dev, void *stored_dev);
+int lbm_costate_from_stored(lbm_ctx *ctx, const void *stored_dev, void *public_dev);
+
 /* Number of time steps advanced since creation or the last set_* call. */
 int64_t lbm_steps_done(const lbm_ctx *ctx);
 

@@ -85,6 +85,10 @@ def load() -> ctypes.CDLL:
         "lbm_load_state": (c_int, [c_void, c_void]),
         "lbm_step_state": (c_int, [c_void, c_void, c_void]),
         "lbm_adjoint_step": (c_int, [c_void, c_void, c_void, c_void, c_void]),
+        "lbm_adjoint_step_stored": (c_int, [c_void, c_void, c_void, c_void, c_void]),
+        "lbm_costate_bytes": (c_int, [c_void, P(ctypes.c_int64)]),
+        "lbm_costate_to_stored": (c_int, [c_void, c_void, c_void]),
+        "lbm_costate_from_stored": (c_int, [c_void, c_void, c_void]),
         "lbm_steps_done": (ctypes.c_int64, [c_void]),
         "lbm_strerror": (ctypes.c_char_p, [c_int]),
         "lbm_last_error": (ctypes.c_char_p, [c_void]),

@@ -13,7 +13,8 @@ whose backward is the library's discrete adjoint step:
             add each step's dL/dtau on the device (FP64).
 
 Per step of the backward pass the device moves one forward step (recompute)
-plus one adjoint step; no state is copied besides the checkpoints.
+plus one adjoint step; no state is copied besides the checkpoints, and the
+co-state stays in the library's stored layout until the end.
 ``tau`` is a 0-d tensor whose value must equal the context's relaxation
 time; its gradient is dL/dtau (two species: at fixed surface tension sigma,
 so the perturbation amplitude A = 9 sigma/(2 tau) moves with tau).  The
@@ -54,9 +55,11 @@ class MomentLBRollout(torch.autograd.Function):
     def backward(ctx, grad_MT: torch.Tensor):
         sim, nsteps, K, ckpts = ctx.sim, ctx.nsteps, ctx.K, ctx.ckpts
         rdt = sim.real_dtype
-        lam = grad_MT.to(rdt).contiguous()
-        lam_b = torch.empty_like(lam)
-        dtau = torch.zeros(1, dtype=torch.float64, device=lam.device)
+        # The co-state stays in the library's stored layout between steps.
+        pub = grad_MT.to(rdt).contiguous()
+        lam, lam_b = sim.new_costate(), sim.new_costate()
+        sim.costate_to_stored(pub, lam)
+        dtau = torch.zeros(1, dtype=torch.float64, device=pub.device)
         slots = [None] + [sim.new_checkpoint() for _ in range(min(K, nsteps) - 1)]
         for s in reversed(range(len(ckpts))):
             n = min(K, nsteps - s * K)
@@ -64,9 +67,10 @@ class MomentLBRollout(torch.autograd.Function):
             for t in range(1, n):
                 sim.step_state(slots[t - 1], slots[t])
             for t in reversed(range(n)):
-                sim.adjoint_step(slots[t], lam, lam_b, dtau)
+                sim.adjoint_step_stored(slots[t], lam, lam_b, dtau)
                 lam, lam_b = lam_b, lam
-        grad_M0 = lam.to(ctx.M0_dtype)
+        sim.costate_from_stored(lam, pub)
+        grad_M0 = pub.to(ctx.M0_dtype)
         grad_tau = dtau.reshape(()).to(grad_MT.dtype)
         return grad_M0, grad_tau, None, None, None
 

@@ -62,7 +62,9 @@ __device__ __forceinline__ void adjoint_layer(const R *l, Layer<R> &o)
     }
 }
 
-template <int Q, class S, int TX, int TY>
+// LSTORED: co-states in the stored (blocked) layout of the state instead of
+// the public one.
+template <int Q, class S, int TX, int TY, bool LSTORED>
 __global__ __launch_bounds__(TX *TY) void k_adjoint_tile(const S *__restrict__ state,
                                                          const typename Store<S>::real *__restrict__ lam_in,
                                                          typename Store<S>::real *__restrict__ lam_out, TileGrid g,
@@ -103,8 +105,12 @@ __global__ __launch_bounds__(TX *TY) void k_adjoint_tile(const S *__restrict__ s
         else { hx = HX - 1; hy = 1 + (m - 2 * HX - TY); }
         hr = hy * HX + hx;
     }
+    // Co-state offsets (field stride LF, plane stride LP) in the chosen layout.
+    const int64_t LF = LSTORED ? (int64_t)kBlock : g.N;
+    const int64_t LP = LSTORED ? g.lay.plane : plane;
     auto xy_of = [&](int h) -> int64_t {
-        return (int64_t)wrap_coord(x0 - 1 + h % HX, g.nx) + (int64_t)g.nx * wrap_coord(y0 - 1 + h / HX, g.ny);
+        const int x = wrap_coord(x0 - 1 + h % HX, g.nx), y = wrap_coord(y0 - 1 + h / HX, g.ny);
+        return LSTORED ? g.lay.xy(x, y) : (int64_t)x + (int64_t)g.nx * y;
     };
     const int64_t own_xy = xy_of(h0);
     const int64_t ring_xy = has_ring ? xy_of(hr) : 0;
@@ -119,10 +125,10 @@ __global__ __launch_bounds__(TX *TY) void k_adjoint_tile(const S *__restrict__ s
     auto fetch = [&](int p, R *own, R *ring) {
         const int zs = p < 0 ? p + g.nz : (p >= g.nz ? p - g.nz : p);
 #pragma unroll
-        for (int k = 0; k < 10; ++k) own[k] = lam_in[k * g.N + own_xy + (int64_t)zs * plane];
+        for (int k = 0; k < 10; ++k) own[k] = lam_in[k * LF + own_xy + (int64_t)zs * LP];
         if (has_ring) {
 #pragma unroll
-            for (int k = 0; k < 10; ++k) ring[k] = lam_in[k * g.N + ring_xy + (int64_t)zs * plane];
+            for (int k = 0; k < 10; ++k) ring[k] = lam_in[k * LF + ring_xy + (int64_t)zs * LP];
         }
     };
 
@@ -159,8 +165,8 @@ __global__ __launch_bounds__(TX *TY) void k_adjoint_tile(const S *__restrict__ s
     };
 
     auto finish = [&](int d) {
-        const int64_t o = (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)d * plane;  // public
-        const int64_t so = g.lay.xy(x0 + lx, y0 + ly) + (int64_t)d * g.lay.plane;           // stored
+        const int64_t so = g.lay.xy(x0 + lx, y0 + ly) + (int64_t)d * g.lay.plane;  // stored
+        const int64_t o = LSTORED ? so : (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)d * plane;
         const MomentAcc<R> &a = acc[0];
         const R dr = Store<S>::load(state[so]);
         const R jx = Store<S>::load(state[kBlock + so]), jy = Store<S>::load(state[2 * kBlock + so]),
@@ -181,15 +187,15 @@ __global__ __launch_bounds__(TX *TY) void k_adjoint_tile(const S *__restrict__ s
         const R tr = (gxx + gyy) + gzz;
         lam_out[o] = fma_(-omega * inv_rho * inv_rho, jGj, fma_(-om1 * R(1.0 / 3.0), tr, a.r));
         const R two_om = R(2) * omega * inv_rho;
-        lam_out[g.N + o] = fma_(two_om, Gjx, R(3) * a.jx);
-        lam_out[2 * g.N + o] = fma_(two_om, Gjy, R(3) * a.jy);
-        lam_out[3 * g.N + o] = fma_(two_om, Gjz, R(3) * a.jz);
-        lam_out[4 * g.N + o] = om1 * gxx;
-        lam_out[5 * g.N + o] = om1 * gyy;
-        lam_out[6 * g.N + o] = om1 * gzz;
-        lam_out[7 * g.N + o] = R(2) * om1 * gxy;
-        lam_out[8 * g.N + o] = R(2) * om1 * gxz;
-        lam_out[9 * g.N + o] = R(2) * om1 * gyz;
+        lam_out[LF + o] = fma_(two_om, Gjx, R(3) * a.jx);
+        lam_out[2 * LF + o] = fma_(two_om, Gjy, R(3) * a.jy);
+        lam_out[3 * LF + o] = fma_(two_om, Gjz, R(3) * a.jz);
+        lam_out[4 * LF + o] = om1 * gxx;
+        lam_out[5 * LF + o] = om1 * gyy;
+        lam_out[6 * LF + o] = om1 * gzz;
+        lam_out[7 * LF + o] = R(2) * om1 * gxy;
+        lam_out[8 * LF + o] = R(2) * om1 * gxz;
+        lam_out[9 * LF + o] = R(2) * om1 * gyz;
         // Gamma : (j j/rho - S)
         const double e = (double)(gxx * (jx * jx * inv_rho - s[0]) + gyy * (jy * jy * inv_rho - s[1]) +
                                   gzz * (jz * jz * inv_rho - s[2])) +
@@ -250,7 +256,7 @@ __global__ __launch_bounds__(256) void k_add_partials(const double *__restrict__
 
 template <int Q, class S, int TX, int TY, int WG_PER_CU>
 hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out, double *partials,
-               int max_partials, double *dtau_accum)
+               int max_partials, double *dtau_accum, bool stored)
 {
     using R = typename Store<S>::real;
     TileGrid g;
@@ -265,9 +271,14 @@ hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *la
     g.chunks = (c->nz + g.zchunk - 1) / g.zchunk;
     const int64_t blocks = (int64_t)g.tiles_x * g.tiles_y * g.chunks;
     if (blocks > max_partials) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_adjoint_tile<Q, S, TX, TY>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
-                       static_cast<const S *>(state), static_cast<const R *>(lam_in), static_cast<R *>(lam_out), g,
-                       (R)c->omega, (R)(1.0 / c->s_pi), partials);
+    if (stored)
+        hipLaunchKernelGGL((k_adjoint_tile<Q, S, TX, TY, true>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
+                           static_cast<const S *>(state), static_cast<const R *>(lam_in), static_cast<R *>(lam_out), g,
+                           (R)c->omega, (R)(1.0 / c->s_pi), partials);
+    else
+        hipLaunchKernelGGL((k_adjoint_tile<Q, S, TX, TY, false>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
+                           static_cast<const S *>(state), static_cast<const R *>(lam_in), static_cast<R *>(lam_out), g,
+                           (R)c->omega, (R)(1.0 / c->s_pi), partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !dtau_accum) return e;
     // dL/dtau = dL/domega * domega/dtau = -omega^2 dL/domega
@@ -278,13 +289,13 @@ hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *la
 
 template <int Q>
 hipError_t dispatch(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out, double *partials,
-                    int max_partials, double *dtau)
+                    int max_partials, double *dtau, bool st)
 {
     switch (c->storage) {
-    case LBM_STORE_F64: return run<Q, double, 32, 8, 1>(c, state, lam_in, lam_out, partials, max_partials, dtau);
-    case LBM_STORE_F32: return run<Q, float, 32, 16, 1>(c, state, lam_in, lam_out, partials, max_partials, dtau);
-    case LBM_STORE_F16: return run<Q, f16, 32, 16, 1>(c, state, lam_in, lam_out, partials, max_partials, dtau);
-    case LBM_STORE_BF16: return run<Q, bf16, 32, 16, 1>(c, state, lam_in, lam_out, partials, max_partials, dtau);
+    case LBM_STORE_F64: return run<Q, double, 32, 8, 1>(c, state, lam_in, lam_out, partials, max_partials, dtau, st);
+    case LBM_STORE_F32: return run<Q, float, 32, 16, 1>(c, state, lam_in, lam_out, partials, max_partials, dtau, st);
+    case LBM_STORE_F16: return run<Q, f16, 32, 16, 1>(c, state, lam_in, lam_out, partials, max_partials, dtau, st);
+    case LBM_STORE_BF16: return run<Q, bf16, 32, 16, 1>(c, state, lam_in, lam_out, partials, max_partials, dtau, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -292,11 +303,11 @@ hipError_t dispatch(const lbm_ctx *c, const void *state, const void *lam_in, voi
 } // namespace
 
 hipError_t launch_adjoint_step(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out,
-                               double *dtau_accum)
+                               double *dtau_accum, bool stored)
 {
     if (c->species != 1 || c->scheme != LBM_SCHEME_MOMENT) return hipErrorNotSupported;
-    return c->q == 19 ? dispatch<19>(c, state, lam_in, lam_out, c->partials, kReduceBlocks * 5, dtau_accum)
-                      : dispatch<27>(c, state, lam_in, lam_out, c->partials, kReduceBlocks * 5, dtau_accum);
+    return c->q == 19 ? dispatch<19>(c, state, lam_in, lam_out, c->partials, kReduceBlocks * 5, dtau_accum, stored)
+                      : dispatch<27>(c, state, lam_in, lam_out, c->partials, kReduceBlocks * 5, dtau_accum, stored);
 }
 
 } // namespace lbm

@@ -160,6 +160,7 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     c->elem = storage_bytes(o.storage);
     c->nfields = o.scheme == LBM_SCHEME_MOMENT ? (species == 1 ? 10 : 11) : lattice * species;
     c->lay = lbm::moment_layout(c->nx, c->ny, c->nfields);
+    c->lay3 = lbm::moment_layout(c->nx, c->ny, 3);
     c->state_elems = o.scheme == LBM_SCHEME_MOMENT ? c->lay.plane * c->nz : (int64_t)c->nfields * c->N;
 
     if (o.device >= 0) {
@@ -343,7 +344,7 @@ int lbm_memory_info(const lbm_ctx *c, int64_t *state_bytes, int64_t *step_bytes)
     const int64_t per_copy = (int64_t)c->elem * c->state_elems;
     if (state_bytes)
         *state_bytes = 2 * per_copy + (c->scratch_phi ? (int64_t)sizeof(float) * c->N : 0) +
-                       (c->scratch_adj ? 3 * (int64_t)c->elem * c->N : 0);
+                       (c->scratch_adj ? (int64_t)c->elem * c->lay3.plane * c->nz : 0);
     if (step_bytes) *step_bytes = 2 * (int64_t)c->elem * c->nfields * c->N;
     return LBM_OK;
 }
@@ -389,7 +390,8 @@ int lbm_step_state(lbm_ctx *c, const void *src, void *dst)
     return LBM_OK;
 }
 
-int lbm_adjoint_step(lbm_ctx *c, const void *state, const void *lam_next, void *lam_out, double *dtau_accum)
+static int adjoint_step(lbm_ctx *c, const void *state, const void *lam_next, void *lam_out, double *dtau_accum,
+                        bool stored)
 {
     if (!c) return LBM_EINVAL;
     if (!state || !lam_next || !lam_out || lam_next == lam_out)
@@ -401,16 +403,58 @@ int lbm_adjoint_step(lbm_ctx *c, const void *state, const void *lam_next, void *
     c->err.clear();
     DeviceGuard g(c->device);
     if (c->species == 2 && !c->scratch_adj) {
-        if (hipMalloc(&c->scratch_adj, 3 * c->elem * (size_t)c->N) != hipSuccess) {
+        if (hipMalloc(&c->scratch_adj, c->elem * (size_t)(c->lay3.plane * c->nz)) != hipSuccess) {
             c->scratch_adj = nullptr;
             (void)hipGetLastError();
             return fail(c, LBM_ENOMEM, "adjoint_step: colour-gradient co-state buffer");
         }
     }
-    hipError_t e = c->species == 2 ? lbm::launch_cg_adjoint_step(c, state, lam_next, lam_out, dtau_accum)
-                                   : lbm::launch_adjoint_step(c, state, lam_next, lam_out, dtau_accum);
+    hipError_t e = c->species == 2 ? lbm::launch_cg_adjoint_step(c, state, lam_next, lam_out, dtau_accum, stored)
+                                   : lbm::launch_adjoint_step(c, state, lam_next, lam_out, dtau_accum, stored);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
     return LBM_OK;
+}
+
+int lbm_adjoint_step(lbm_ctx *c, const void *state, const void *lam_next, void *lam_out, double *dtau_accum)
+{
+    return adjoint_step(c, state, lam_next, lam_out, dtau_accum, false);
+}
+
+int lbm_adjoint_step_stored(lbm_ctx *c, const void *state, const void *lam_next, void *lam_out, double *dtau_accum)
+{
+    return adjoint_step(c, state, lam_next, lam_out, dtau_accum, true);
+}
+
+static size_t real_bytes(const lbm_ctx *c) { return c->storage == LBM_STORE_F64 ? 8 : 4; }
+
+int lbm_costate_bytes(const lbm_ctx *c, int64_t *bytes)
+{
+    if (!c || !bytes) return LBM_EINVAL;
+    if (c->scheme != LBM_SCHEME_MOMENT) return fail(c, LBM_ESTATE, "costate_bytes: moment scheme only");
+    *bytes = (int64_t)real_bytes(c) * c->state_elems;
+    return LBM_OK;
+}
+
+static int costate_convert(lbm_ctx *c, const void *src, void *dst, bool to_stored)
+{
+    if (!c) return LBM_EINVAL;
+    if (!src || !dst || src == dst) return fail(c, LBM_EINVAL, "costate conversion: NULL or aliased buffers");
+    if (c->scheme != LBM_SCHEME_MOMENT) return fail(c, LBM_ESTATE, "costate conversion: moment scheme only");
+    c->err.clear();
+    DeviceGuard g(c->device);
+    hipError_t e = lbm::launch_costate_convert(c, src, dst, to_stored);
+    if (e != hipSuccess) return hip_fail(c, e, "costate conversion");
+    return LBM_OK;
+}
+
+int lbm_costate_to_stored(lbm_ctx *c, const void *public_dev, void *stored_dev)
+{
+    return costate_convert(c, public_dev, stored_dev, true);
+}
+
+int lbm_costate_from_stored(lbm_ctx *c, const void *stored_dev, void *public_dev)
+{
+    return costate_convert(c, stored_dev, public_dev, false);
 }
 
 int64_t lbm_steps_done(const lbm_ctx *c) { return c ? c->steps : -1; }

@@ -85,9 +85,12 @@ __device__ __forceinline__ float sqrt_<float>(float x)
     return __builtin_sqrtf(x);
 }
 
-template <int Q, class R, int TX, int TY>
+// LSTORED: co-states in the stored (blocked) layout of the state instead of
+// the public one.
+template <int Q, class R, int TX, int TY, bool LSTORED>
 __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(const R *__restrict__ state, const R *__restrict__ lam_in,
                                                             R *__restrict__ lam_out, R *__restrict__ gG, TileGrid g,
+                                                            MomentLayout lay3,
                                                             R omega, R A9, R beta, double tau,
                                                             double *__restrict__ partials)
 {
@@ -211,8 +214,10 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(const R *__restrict_
     };
 
     auto finish = [&](int dpl) {
-        const int64_t o = (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)dpl * plane;  // public
-        const int64_t so = g.lay.xy(x0 + lx, y0 + ly) + (int64_t)dpl * g.lay.plane;           // stored
+        const int64_t so = g.lay.xy(x0 + lx, y0 + ly) + (int64_t)dpl * g.lay.plane;    // stored
+        const int64_t op = (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)dpl * plane;  // public
+        const int64_t o = LSTORED ? so : op;  // co-states
+        const int64_t LF = LSTORED ? (int64_t)kBlock : g.N;
         const CgAdjAcc<R> &a = acc[0];
         // Own state.
         const R dr = state[so], r1 = state[kBlock + so];
@@ -276,17 +281,17 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(const R *__restrict_
         const R Vn = fma_(a.vx, nx, fma_(a.vy, ny, a.vz * nz));
         const R ir2 = inv_rho * inv_rho;
         lam_out[o] = fma_(sdm * r2, ir2, fma_(Vn * beta * r2 * r2, ir2, lrho));
-        lam_out[g.N + o] = fma_(-sdm * r1, ir2, fma_(Vn * beta * r1 * r1, ir2, lrho));
+        lam_out[LF + o] = fma_(-sdm * r1, ir2, fma_(Vn * beta * r1 * r1, ir2, lrho));
         const R two_om = R(2) * omega * inv_rho;
-        lam_out[2 * g.N + o] = fma_(two_om, Gjx, R(3) * bx);
-        lam_out[3 * g.N + o] = fma_(two_om, Gjy, R(3) * by);
-        lam_out[4 * g.N + o] = fma_(two_om, Gjz, R(3) * bz);
-        lam_out[5 * g.N + o] = om1 * gxx;
-        lam_out[6 * g.N + o] = om1 * gyy;
-        lam_out[7 * g.N + o] = om1 * gzz;
-        lam_out[8 * g.N + o] = R(2) * om1 * gxy;
-        lam_out[9 * g.N + o] = R(2) * om1 * gxz;
-        lam_out[10 * g.N + o] = R(2) * om1 * gyz;
+        lam_out[2 * LF + o] = fma_(two_om, Gjx, R(3) * bx);
+        lam_out[3 * LF + o] = fma_(two_om, Gjy, R(3) * by);
+        lam_out[4 * LF + o] = fma_(two_om, Gjz, R(3) * bz);
+        lam_out[5 * LF + o] = om1 * gxx;
+        lam_out[6 * LF + o] = om1 * gyy;
+        lam_out[7 * LF + o] = om1 * gzz;
+        lam_out[8 * LF + o] = R(2) * om1 * gxy;
+        lam_out[9 * LF + o] = R(2) * om1 * gxz;
+        lam_out[10 * LF + o] = R(2) * om1 * gyz;
         // Co-state of G.
         const R GGx = fma_(gxx, Gx, fma_(gxy, Gy, gxz * Gz));
         const R GGy = fma_(gxy, Gx, fma_(gyy, Gy, gyz * Gz));
@@ -300,9 +305,10 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(const R *__restrict_
             const R pert = A9 * (R(2) * fma_(-tr, Ga, GGa) * invD - num * Ga * invD3);
             return fma_(C, fma_(-Ga * GV, invD3, Va * invD), pert);
         };
-        gG[o] = gcomp(GGx, Gx, a.vx);
-        gG[g.N + o] = gcomp(GGy, Gy, a.vy);
-        gG[2 * g.N + o] = gcomp(GGz, Gz, a.vz);
+        const int64_t og = lay3.xy(x0 + lx, y0 + ly) + (int64_t)dpl * lay3.plane;  // scratch, 3-field blocks
+        gG[og] = gcomp(GGx, Gx, a.vx);
+        gG[kBlock + og] = gcomp(GGy, Gy, a.vy);
+        gG[2 * kBlock + og] = gcomp(GGz, Gz, a.vz);
         // tau-sensitivity at fixed sigma.
         const R sxx = s[0], syy = s[1], szz = s[2], sxy = s[3], sxz = s[4], syz = s[5];
         const double eo = (double)(gxx * (jx * jx * inv_rho - sxx) + gyy * (jy * jy * inv_rho - syy) +
@@ -316,12 +322,14 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(const R *__restrict_
 
     R la[11], lb[11], rla[11], rlb[11];
     auto fetch = [&](int p, R *own, R *ring) {
-        const int64_t zo = zoff(p);
+        const int64_t LF = LSTORED ? (int64_t)kBlock : g.N;
+        const int64_t zo = LSTORED ? (int64_t)zs_of(p) * g.lay.plane : zoff(p);
+        const int64_t oxy = LSTORED ? own_sxy : own_xy, rxy = LSTORED ? ring_sxy : ring_xy;
 #pragma unroll
-        for (int k = 0; k < 11; ++k) own[k] = lam_in[k * g.N + own_xy + zo];
+        for (int k = 0; k < 11; ++k) own[k] = lam_in[k * LF + oxy + zo];
         if (has_ring) {
 #pragma unroll
-            for (int k = 0; k < 11; ++k) ring[k] = lam_in[k * g.N + ring_xy + zo];
+            for (int k = 0; k < 11; ++k) ring[k] = lam_in[k * LF + rxy + zo];
         }
     };
 
@@ -369,9 +377,9 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(const R *__restrict_
 // the tile plus a one-node halo ring are kept for planes z-1, z, z+1 in an LDS
 // ring, so each gG value is read from HBM about once (a one-thread-per-node
 // stencil re-reads the neighbouring planes from memory).
-template <int Q, class R, int TX, int TY>
+template <int Q, class R, int TX, int TY, bool LSTORED>
 __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_phi(const R *__restrict__ state, const R *__restrict__ gG,
-                                                           R *__restrict__ lam_out, TileGrid g)
+                                                           R *__restrict__ lam_out, TileGrid g, MomentLayout lay3)
 {
     using L = Lattice<Q>;
     constexpr int NT = TX * TY;
@@ -404,8 +412,8 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_phi(const R *__restrict__
         else { hx = HX - 1; hy = 1 + (m - 2 * HX - TY); }
         hr = hy * HX + hx;
     }
-    auto xy_of = [&](int h) -> int64_t {
-        return (int64_t)wrap_coord(x0 - 1 + h % HX, g.nx) + (int64_t)g.nx * wrap_coord(y0 - 1 + h / HX, g.ny);
+    auto xy_of = [&](int h) -> int64_t {  // in the 3-field blocked layout of gG
+        return lay3.xy(wrap_coord(x0 - 1 + h % HX, g.nx), wrap_coord(y0 - 1 + h / HX, g.ny));
     };
     const int64_t own_xy = xy_of(h0);
     const int64_t ring_xy = has_ring ? xy_of(hr) : 0;
@@ -414,12 +422,12 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_phi(const R *__restrict__
 
     R go[3], gr[3];
     auto fetch = [&](int p) {
-        const int64_t zo = (int64_t)zs_of(p) * plane;
+        const int64_t zo = (int64_t)zs_of(p) * lay3.plane;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) go[a] = gG[a * g.N + own_xy + zo];
+        for (int a = 0; a < 3; ++a) go[a] = gG[a * kBlock + own_xy + zo];
         if (has_ring) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) gr[a] = gG[a * g.N + ring_xy + zo];
+            for (int a = 0; a < 3; ++a) gr[a] = gG[a * kBlock + ring_xy + zo];
         }
     };
     auto publish = [&](int p) {
@@ -459,12 +467,13 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_phi(const R *__restrict__
                 if (cz) c = cz > 0 ? c + d[2 * HN + h] : c - d[2 * HN + h];
                 gphi = fma_(R(3.0 * L::w(k)), c, gphi);
             }
-            const int64_t n = (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)p * plane;
             const int64_t so = g.lay.xy(x0 + lx, y0 + ly) + (int64_t)p * g.lay.plane;
+            const int64_t n = LSTORED ? so : (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)p * plane;
+            const int64_t LF = LSTORED ? (int64_t)kBlock : g.N;
             const R rho = R(1) + state[so], r1 = state[kBlock + so], r2 = rho - r1;
             const R k2 = R(2) * gphi / (rho * rho);
             lam_out[n] = fma_(k2, r2, lam_out[n]);
-            lam_out[g.N + n] = fma_(-k2, r1, lam_out[g.N + n]);
+            lam_out[LF + n] = fma_(-k2, r1, lam_out[LF + n]);
         }
         __syncthreads();
     }
@@ -485,7 +494,7 @@ __global__ __launch_bounds__(256) void k_cg_add_partials(const double *__restric
     if (threadIdx.x == 0) *accum += sh[0];
 }
 
-template <int Q, class R, int TX, int TY>
+template <int Q, class R, int TX, int TY, bool LSTORED>
 hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out, double *dtau)
 {
     TileGrid g;
@@ -501,9 +510,9 @@ hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *la
     const int64_t blocks = (int64_t)g.tiles_x * g.tiles_y * g.chunks;
     if (blocks > 5 * kReduceBlocks) return hipErrorInvalidConfiguration;
     R *gG = static_cast<R *>(c->scratch_adj);
-    hipLaunchKernelGGL((k_cg_adjoint_tile<Q, R, TX, TY>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
+    hipLaunchKernelGGL((k_cg_adjoint_tile<Q, R, TX, TY, LSTORED>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
                        static_cast<const R *>(state), static_cast<const R *>(lam_in), static_cast<R *>(lam_out), gG,
-                       g, (R)c->omega, (R)(c->A / 9.0), (R)c->beta, c->tau, c->partials);
+                       g, c->lay3, (R)c->omega, (R)(c->A / 9.0), (R)c->beta, c->tau, c->partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     TileGrid gp = g;
@@ -513,27 +522,34 @@ hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *la
     gp.chunks = (c->nz + gp.zchunk - 1) / gp.zchunk;
     const int64_t pblocks = (int64_t)gp.tiles_x * gp.tiles_y * gp.chunks;
     if (pblocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_cg_adjoint_phi<Q, R, 64, 16>), dim3((unsigned)pblocks), dim3(1024), 0, c->stream,
-                       static_cast<const R *>(state), static_cast<const R *>(gG), static_cast<R *>(lam_out), gp);
+    hipLaunchKernelGGL((k_cg_adjoint_phi<Q, R, 64, 16, LSTORED>), dim3((unsigned)pblocks), dim3(1024), 0, c->stream,
+                       static_cast<const R *>(state), static_cast<const R *>(gG), static_cast<R *>(lam_out), gp, c->lay3);
     e = hipGetLastError();
     if (e != hipSuccess || !dtau) return e;
     hipLaunchKernelGGL(k_cg_add_partials, dim3(1), dim3(256), 0, c->stream, c->partials, (int)blocks, dtau);
     return hipGetLastError();
 }
 
+template <bool LS>
+hipError_t dispatch(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out, double *dtau)
+{
+    if (c->storage == LBM_STORE_F32)
+        return c->q == 19 ? run<19, float, 64, 4, LS>(c, state, lam_in, lam_out, dtau)
+                          : run<27, float, 32, 8, LS>(c, state, lam_in, lam_out, dtau);
+    if (c->storage == LBM_STORE_F64)
+        return c->q == 19 ? run<19, double, 32, 8, LS>(c, state, lam_in, lam_out, dtau)
+                          : run<27, double, 32, 8, LS>(c, state, lam_in, lam_out, dtau);
+    return hipErrorNotSupported;
+}
+
 } // namespace
 
 hipError_t launch_cg_adjoint_step(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out,
-                                  double *dtau_accum)
+                                  double *dtau_accum, bool stored)
 {
     if (c->species != 2 || !c->scratch_adj) return hipErrorNotSupported;
-    if (c->storage == LBM_STORE_F32)
-        return c->q == 19 ? run<19, float, 32, 8>(c, state, lam_in, lam_out, dtau_accum)
-                          : run<27, float, 32, 8>(c, state, lam_in, lam_out, dtau_accum);
-    if (c->storage == LBM_STORE_F64)
-        return c->q == 19 ? run<19, double, 32, 8>(c, state, lam_in, lam_out, dtau_accum)
-                          : run<27, double, 32, 8>(c, state, lam_in, lam_out, dtau_accum);
-    return hipErrorNotSupported;
+    return stored ? dispatch<true>(c, state, lam_in, lam_out, dtau_accum)
+                  : dispatch<false>(c, state, lam_in, lam_out, dtau_accum);
 }
 
 } // namespace lbm

@@ -86,6 +86,22 @@ __global__ void k_get_moment_state(const S *__restrict__ st, T *__restrict__ dst
     }
 }
 
+// ---- co-states ----------------------------------------------------------------
+
+template <class R>
+__global__ void k_costate_convert(const R *__restrict__ src, R *__restrict__ dst, int64_t N, int nx, int ny,
+                                  MomentLayout lay, int nf, bool to_stored)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int64_t so = stored_node(lay, n, nx, ny);
+    if (to_stored) {
+        for (int k = 0; k < nf; ++k) dst[k * kBlock + so] = src[k * N + n];
+    } else {
+        for (int k = 0; k < nf; ++k) dst[k * N + n] = src[k * kBlock + so];
+    }
+}
+
 // ---- population scheme -------------------------------------------------------------
 
 // A_i[y] = shifted R(M(y + c_i))_i (Eq. 4 without collision).
@@ -456,6 +472,19 @@ hipError_t launch_reduce(const lbm_ctx *c, const void *state)
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kThreads), 0, c->stream, c->partials, kReduceBlocks,
                        c->red_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_costate_convert(const lbm_ctx *c, const void *src, void *dst, bool to_stored)
+{
+    if (c->storage == LBM_STORE_F64)
+        hipLaunchKernelGGL((k_costate_convert<double>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
+                           static_cast<const double *>(src), static_cast<double *>(dst), c->N, c->nx, c->ny, c->lay,
+                           c->nfields, to_stored);
+    else
+        hipLaunchKernelGGL((k_costate_convert<float>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
+                           static_cast<const float *>(src), static_cast<float *>(dst), c->N, c->nx, c->ny, c->lay,
+                           c->nfields, to_stored);
     return hipGetLastError();
 }
 

@@ -21,12 +21,13 @@ struct lbm_ctx {
     size_t elem = 4;  // bytes per stored element
     int64_t state_elems = 0;  // elements per state copy (blocked moment layout or q x N populations)
     lbm::MomentLayout lay{};  // stored layout of the moment scheme
+    lbm::MomentLayout lay3{}; // 3-field blocked layout of the two-species adjoint's scratch
     void *state[2] = {nullptr, nullptr};
     int cur = 0;      // state[cur] holds the current time level
     double *partials = nullptr;  // FP64 reduction partials (kReduceBlocks x 5)
     double *red_out = nullptr;   // 5 device doubles
     float *scratch_phi = nullptr; // phase field of the two-species population scheme
-    void *scratch_adj = nullptr;  // co-state of the colour gradient (3 N reals), two-species adjoint
+    void *scratch_adj = nullptr;  // co-state of the colour gradient (3 fields, layout lay3), two-species adjoint
     int64_t steps = 0;
     mutable std::string err;
 };
@@ -41,14 +42,20 @@ hipError_t launch_moment_step(const lbm_ctx *c, const void *in, void *out);
 // Moment scheme, two species (colour gradient).
 hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out);
 
-// Discrete adjoint of the one-species moment step.
+// Discrete adjoint of the one-species moment step; co-states in the public
+// layout, or in the stored (blocked) layout of the state if `stored`.
 hipError_t launch_adjoint_step(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out,
-                               double *dtau_accum);
+                               double *dtau_accum, bool stored);
 
 // Discrete adjoint of the two-species (colour-gradient) moment step; uses
-// c->scratch_adj (3 N reals) for the co-state of the colour gradient.
+// c->scratch_adj (3 fields in the blocked layout lay3) for the co-state of
+// the colour gradient.
 hipError_t launch_cg_adjoint_step(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out,
-                                  double *dtau_accum);
+                                  double *dtau_accum, bool stored);
+
+// Co-state (real type of the context, nfields fields) between the public
+// layout (nfields x N) and the stored blocked layout (state_elems elements).
+hipError_t launch_costate_convert(const lbm_ctx *c, const void *src, void *dst, bool to_stored);
 
 // Population scheme.
 hipError_t launch_population_step(const lbm_ctx *c, const void *in, void *out);

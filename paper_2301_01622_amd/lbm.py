@@ -165,6 +165,38 @@ class LBM:
                                               ctypes.c_void_p(lam_next.data_ptr()),
                                               ctypes.c_void_p(lam_out.data_ptr()), dptr), self._ctx, "adjoint_step")
 
+    # ---- co-states in the stored layout -----------------------------------
+    @property
+    def costate_bytes(self) -> int:
+        b = ctypes.c_int64()
+        _lib.check(self._lib.lbm_costate_bytes(self._ctx, ctypes.byref(b)), self._ctx, "costate_bytes")
+        return b.value
+
+    def new_costate(self) -> torch.Tensor:
+        """A zeroed device buffer for one co-state in the stored layout."""
+        n = self.costate_bytes // torch.tensor([], dtype=self.real_dtype).element_size()
+        return torch.zeros(n, dtype=self.real_dtype, device=self.device)
+
+    def costate_to_stored(self, public: torch.Tensor, stored: torch.Tensor) -> None:
+        assert public.dtype == self.real_dtype and public.is_contiguous() and public.is_cuda
+        _lib.check(self._lib.lbm_costate_to_stored(self._ctx, ctypes.c_void_p(public.data_ptr()),
+                                                   ctypes.c_void_p(stored.data_ptr())), self._ctx, "costate_to_stored")
+
+    def costate_from_stored(self, stored: torch.Tensor, public: torch.Tensor) -> None:
+        assert public.dtype == self.real_dtype and public.is_contiguous() and public.is_cuda
+        _lib.check(self._lib.lbm_costate_from_stored(self._ctx, ctypes.c_void_p(stored.data_ptr()),
+                                                     ctypes.c_void_p(public.data_ptr())), self._ctx,
+                   "costate_from_stored")
+
+    def adjoint_step_stored(self, state: torch.Tensor, lam_next: torch.Tensor, lam_out: torch.Tensor,
+                            dtau_accum: torch.Tensor | None = None) -> None:
+        """adjoint_step with both co-states in the stored layout (new_costate buffers)."""
+        dptr = ctypes.c_void_p(dtau_accum.data_ptr()) if dtau_accum is not None else None
+        _lib.check(self._lib.lbm_adjoint_step_stored(self._ctx, ctypes.c_void_p(state.data_ptr()),
+                                                     ctypes.c_void_p(lam_next.data_ptr()),
+                                                     ctypes.c_void_p(lam_out.data_ptr()), dptr), self._ctx,
+                   "adjoint_step_stored")
+
     @property
     def steps_done(self) -> int:
         return int(self._lib.lbm_steps_done(self._ctx))
