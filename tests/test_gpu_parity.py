@@ -80,6 +80,20 @@ def test_ragged_random_state(LBM, oracle, q, storage, tol):
 
 
 @pytest.mark.parametrize("q", [19, 27])
+def test_wide_tile_random_state(LBM, oracle, q):
+    """nx a multiple of 256 selects 256 x 4 tiles (whose x-halo wraps onto the
+    same tile at nx = 256); small y and z keep the oracle fast."""
+    shape = (9, 11, 256)
+    _say(f"wide tiles {shape} D3Q{q} f32 10 steps")
+    H = I.random_moments(shape, seed=140 + q)
+    ref = oracle.moment_run(H, q, 0.66, 10)
+    got = _gpu_run_from_moments(LBM, H, q, 0.66, 10, storage="f32")
+    err = np.abs(got - ref).max(axis=(1, 2, 3))
+    _say(f"  max err per field {err}")
+    assert err.max() <= 1e-6
+
+
+@pytest.mark.parametrize("q", [19, 27])
 def test_minimum_box(LBM, oracle, q):
     """Smallest allowed box (3 nodes per side): every neighbour wraps."""
     H = I.random_moments((3, 3, 3), seed=7)
@@ -219,4 +233,17 @@ def test_translation_bitwise(LBM, q, storage):
     Hs = np.ascontiguousarray(np.roll(H, shift, axis=(1, 2, 3)))
     a = _gpu_run_from_moments(LBM, H, q, 0.6, 6, storage=storage)
     b = _gpu_run_from_moments(LBM, Hs, q, 0.6, 6, storage=storage)
+    np.testing.assert_array_equal(np.roll(a, shift, axis=(1, 2, 3)), b)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_translation_bitwise_wide_tiles(LBM, storage):
+    """The same for the 256 x 4 tiles (nx = 256): an x-shift that is not a
+    multiple of 64 moves nodes across the four stored blocks of a tile row."""
+    shape = (6, 10, 256)
+    H = I.random_moments(shape, seed=78)
+    shift = (2, 3, 37)
+    Hs = np.ascontiguousarray(np.roll(H, shift, axis=(1, 2, 3)))
+    a = _gpu_run_from_moments(LBM, H, 27, 0.6, 6, storage=storage)
+    b = _gpu_run_from_moments(LBM, Hs, 27, 0.6, 6, storage=storage)
     np.testing.assert_array_equal(np.roll(a, shift, axis=(1, 2, 3)), b)
