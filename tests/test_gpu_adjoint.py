@@ -1,6 +1,8 @@
 """GPU parity of the discrete adjoint (one species) against the oracle's
 adjoint, K-independence of the checkpointed rollout, and a central
 finite-difference check of the rollout gradient."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -175,3 +177,36 @@ def test_adjoint_step_stored_layout_bitwise(mods, oracle, species, storage):
     assert torch.equal(back, ln)
     assert torch.equal(lo2, lo)
     assert float(d_st) == float(d_pub)
+
+
+def test_adjoint_entry_points_reject_bad_calls(mods):
+    """Error behaviour of the adjoint and co-state entry points: aliased or
+    NULL buffers are LBM_EINVAL, the population scheme is LBM_ESTATE; nothing
+    is launched in either case."""
+    LBM, _ = mods
+    from paper_2301_01622_amd import _lib
+    lib = _lib.load()
+    sim = LBM((20, 18, 16), 19, 0.7, storage="f32")
+    st = sim.new_checkpoint()
+    sim.save_state(st)
+    lam = sim.new_costate()
+    p = ctypes.c_void_p
+    ctx = sim._ctx
+    assert lib.lbm_adjoint_step_stored(ctx, p(st.data_ptr()), p(lam.data_ptr()), p(lam.data_ptr()), None) == \
+        _lib.LBM_EINVAL
+    assert lib.lbm_adjoint_step(ctx, None, p(lam.data_ptr()), p(st.data_ptr()), None) == _lib.LBM_EINVAL
+    assert lib.lbm_costate_to_stored(ctx, p(lam.data_ptr()), p(lam.data_ptr())) == _lib.LBM_EINVAL
+    assert lib.lbm_costate_from_stored(ctx, None, p(lam.data_ptr())) == _lib.LBM_EINVAL
+    assert lib.lbm_costate_bytes(ctx, None) == _lib.LBM_EINVAL
+    sim.close()
+    pop = LBM((20, 18, 16), 19, 0.7, storage="f32", scheme="population")
+    b = ctypes.c_int64()
+    assert lib.lbm_costate_bytes(pop._ctx, ctypes.byref(b)) == _lib.LBM_ESTATE
+    buf = torch.zeros(16, device="cuda")
+    buf2 = torch.zeros(16, device="cuda")
+    assert lib.lbm_adjoint_step(pop._ctx, p(buf.data_ptr()), p(buf.data_ptr() + 4), p(buf2.data_ptr()), None) == \
+        _lib.LBM_ESTATE
+    assert lib.lbm_costate_to_stored(pop._ctx, p(buf.data_ptr()), p(buf2.data_ptr())) == _lib.LBM_ESTATE
+    assert "moment scheme" in lib.lbm_last_error(pop._ctx).decode()
+    torch.cuda.synchronize()
+    pop.close()
