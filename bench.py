@@ -3,8 +3,9 @@
 Workload: 256^3 periodic box, D3Q27, one component, FP32 moments
 (rho, j, P: 10 values per node), tau = 0.6, random solenoidal velocity
 (seed 16220002, max |u| = 1e-3).  A step is one full time step of the
-scheme (one fused kernel launch).  The population-storing BGK scheme is
-timed on the same box and GPU, and the FP64 CPU oracle on the host cores.
+scheme (one fused kernel launch).  The population-storing BGK scheme (two
+copies, and in place with one copy) is timed on the same box and GPU, and the
+FP64 CPU oracle on the host cores.
 
 Prints one JSON line (see the keys below).  MLUPS follows the paper's
 definition (Sec. III.C): nodes / (1e6 x seconds per step).
@@ -224,6 +225,23 @@ def main() -> int:
             del buf
         sim.close()
 
+        # The paper's split approach on the same box: a collision pass, then
+        # the streaming pass (same results, more bytes moved).
+        sp = LBM((n, n, n), q, tau, storage="f32", stream=stream, split=True)
+        sp.set_equilibrium(rho_d, u_d)
+        sms = time_steps(sp, stream, args.steps, args.warmup)
+        _, s_step = sp.memory_info()
+        sp.close()
+        split = {
+            "scheme": "moment LB as the split approach (collision pass + streaming pass, two launches)",
+            "value": round(N / (sms * 1e-3) / 1e6, 1),
+            "unit": "MLUPS",
+            "ms_per_step": round(sms, 5),
+            "bytes_per_node_step": s_step // N,
+            "hbm_frac": round(s_step / (sms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "fused_speedup": round(sms / ms, 3),
+        }
+
         pop = None
         if not args.no_population:
             ps = LBM((n, n, n), q, tau, storage="f32", scheme="population", stream=stream)
@@ -237,6 +255,21 @@ def main() -> int:
                 "ms_per_step": round(pms, 5),
                 "hbm_frac": round(p_step / (pms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 "bytes_per_node_state": p_state // N,
+            }
+            # The same BGK scheme in place (AA pattern): one copy of the
+            # populations, the same bytes moved per step.
+            pa = LBM((n, n, n), q, tau, storage="f32", scheme="population_aa", stream=stream)
+            pa.set_equilibrium(rho_d, u_d)
+            ams = time_steps(pa, stream, args.steps, args.warmup)
+            a_state, a_step = pa.memory_info()
+            pa.close()
+            pop["in_place"] = {
+                "scheme": "population-storing BGK in place (AA pattern, one copy)",
+                "value": round(N / (ams * 1e-3) / 1e6, 1),
+                "unit": "MLUPS",
+                "ms_per_step": round(ams, 5),
+                "hbm_frac": round(a_step / (ams * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "bytes_per_node_state": a_state // N,
             }
 
     two = None
@@ -282,12 +315,14 @@ def main() -> int:
         line["roofline"]["traffic_bytes_per_launch"] = traffic_bytes
         line["roofline"]["traffic_over_algorithmic"] = round(traffic_bytes / step_bytes, 4)
     line["adjoint"] = adjoint
+    line["split_approach"] = split
     if two:
         line["two_component"] = two
     if copy:
         line["roofline"]["frac_of_measured_copy"] = round(achieved / copy["gbs"], 4)
     if pop:
         line["speedup_vs_population_lb"] = round(mlups / pop["value"], 3)
+        line["speedup_vs_population_lb_in_place"] = round(mlups / pop["in_place"]["value"], 3)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n, q, tau, args.cpu_steps, rho, u)
     print(json.dumps(line), flush=True)

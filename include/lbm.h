@@ -57,6 +57,11 @@ extern "C" {
 #define LBM_SCHEME_MOMENT 0     /* the paper's method: moments only (default) */
 #define LBM_SCHEME_POPULATION 1 /* population-storing BGK, A-B buffers (baseline); two species:
                                    colour-gradient LB with 2q stored populations, FP32 */
+#define LBM_SCHEME_POPULATION_AA 2 /* population-storing BGK in place (AA pattern: one copy of the
+                                      q arrays, steps alternate between a neighbour-access and a
+                                      node-local update); one species, FP32 or FP64; the stronger
+                                      memory baseline.  lbm_save_state / lbm_load_state /
+                                      lbm_step_state and the adjoint return LBM_ESTATE */
 
 /* Device storage of the moment state.  All formats store deviations from the
  * rest state rho = 1, u = 0: delta_rho = rho - 1, j, and
@@ -86,6 +91,13 @@ typedef struct {
     void *stream;    /* hipStream_t to run on; NULL = the null stream */
     int device;      /* HIP device ordinal; -1 = current device */
     int check_every; /* lbm_step runs the FP64 check every this many steps; 0 = never */
+    int split;       /* 0 (default): fused step, one kernel.  1: the paper's split approach
+                        (Sec. III), for comparison: a collision pass relaxes the stored moments
+                        in place (rho, j, S) -> (rho, j, S'), then the streaming pass
+                        reconstructs, pulls and sums.  Moment scheme, one species only
+                        (else LBM_EINVAL); results equal the fused step's bit for bit with
+                        FP32/FP64 storage (16-bit storage rounds the stored S'); 36 instead of
+                        20 stored values moved per node; lbm_step_state gives LBM_ESTATE */
 } lbm_opts;
 
 /* Caller-owned moment buffers, see the layout above. */

@@ -18,7 +18,7 @@ LBM_EDEVICE = -3
 LBM_EUNSTABLE = -4
 LBM_ESTATE = -5
 
-SCHEME = {"moment": 0, "population": 1}
+SCHEME = {"moment": 0, "population": 1, "population_aa": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 DTYPE_F64 = 0
 DTYPE_F32 = 1
@@ -38,6 +38,7 @@ class Opts(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("device", ctypes.c_int),
         ("check_every", ctypes.c_int),
+        ("split", ctypes.c_int),
     ]
 
 

@@ -101,6 +101,7 @@ void lbm_default_opts(lbm_opts *o)
     o->stream = nullptr;
     o->device = -1;
     o->check_every = 0;
+    o->split = 0;
 }
 
 const char *lbm_strerror(int code)
@@ -129,7 +130,12 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     if (lattice != 19 && lattice != 27) return LBM_EINVAL;
     if (!(tau > 0.5) || !std::isfinite(tau)) return LBM_EINVAL;
     if (species != 1 && species != 2) return LBM_EINVAL;
-    if (o.scheme != LBM_SCHEME_MOMENT && o.scheme != LBM_SCHEME_POPULATION) return LBM_EINVAL;
+    if (o.scheme != LBM_SCHEME_MOMENT && o.scheme != LBM_SCHEME_POPULATION && o.scheme != LBM_SCHEME_POPULATION_AA)
+        return LBM_EINVAL;
+    if (o.split != 0 && (o.split != 1 || o.scheme != LBM_SCHEME_MOMENT || species != 1)) return LBM_EINVAL;
+    if (o.scheme == LBM_SCHEME_POPULATION_AA &&
+        (species != 1 || (o.storage != LBM_STORE_F32 && o.storage != LBM_STORE_F64)))
+        return LBM_EINVAL;
     if (storage_bytes(o.storage) == 0) return LBM_EINVAL;
     if (o.check_every < 0) return LBM_EINVAL;
     if (o.scheme == LBM_SCHEME_POPULATION && o.storage != LBM_STORE_F32 && o.storage != LBM_STORE_F64)
@@ -157,6 +163,7 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     c->s_pi = o.s_pi > 0.0 ? o.s_pi : (o.storage == LBM_STORE_F16 ? 1024.0 : 1.0);
     c->stream = static_cast<hipStream_t>(o.stream);
     c->check_every = o.check_every;
+    c->split = o.split;
     c->elem = storage_bytes(o.storage);
     c->nfields = o.scheme == LBM_SCHEME_MOMENT ? (species == 1 ? 10 : 11) : lattice * species;
     c->lay = lbm::moment_layout(c->nx, c->ny, c->nfields);
@@ -171,7 +178,8 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     }
     DeviceGuard g(c->device);
     const size_t bytes = c->elem * (size_t)c->state_elems;
-    for (int k = 0; k < 2; ++k) {
+    const int copies = c->scheme == LBM_SCHEME_POPULATION_AA ? 1 : 2;  // in place: one copy
+    for (int k = 0; k < copies; ++k) {
         hipError_t e = hipMalloc(&c->state[k], bytes);
         if (e != hipSuccess) {
             lbm_destroy(c);
@@ -190,7 +198,7 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     }
     // Fluid at rest: every stored deviation is zero (for two species rho1 = 0:
     // species 2 fills the box).
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < copies; ++k) {
         if (hipMemsetAsync(c->state[k], 0, bytes, c->stream) != hipSuccess) {
             lbm_destroy(c);
             return LBM_EDEVICE;
@@ -299,6 +307,10 @@ int lbm_reduce(lbm_ctx *c, double out[5])
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "reduce");
     const double n = (double)c->N;
+    // In place, after an odd number of steps the populations sit in the
+    // reversed slots: the summed momentum changes sign.
+    if (c->scheme == LBM_SCHEME_POPULATION_AA && (c->steps & 1))
+        for (int a = 2; a < 5; ++a) v[a] = -v[a];
     if (c->species == 1) {
         out[0] = n + v[0];
         out[1] = 0.0;
@@ -321,13 +333,24 @@ int lbm_step(lbm_ctx *c, int n)
     c->err.clear();
     DeviceGuard g(c->device);
     for (int t = 0; t < n; ++t) {
-        const void *in = c->state[c->cur];
-        void *out = c->state[1 - c->cur];
-        hipError_t e = c->scheme == LBM_SCHEME_POPULATION ? lbm::launch_population_step(c, in, out)
-                       : c->species == 2                  ? lbm::launch_cg_step(c, in, out)
-                                                          : lbm::launch_moment_step(c, in, out);
+        hipError_t e;
+        if (c->scheme == LBM_SCHEME_POPULATION_AA) {
+            e = lbm::launch_population_aa_step(c, c->state[0], (c->steps & 1) != 0);
+        } else {
+            const void *in = c->state[c->cur];
+            void *out = c->state[1 - c->cur];
+            if (c->split) {
+                // Split approach: relax the current state in place, then stream.
+                e = lbm::launch_moment_collide(c, c->state[c->cur]);
+                if (e == hipSuccess) e = lbm::launch_moment_step(c, in, out, true);
+            } else {
+                e = c->scheme == LBM_SCHEME_POPULATION ? lbm::launch_population_step(c, in, out)
+                    : c->species == 2                  ? lbm::launch_cg_step(c, in, out)
+                                                       : lbm::launch_moment_step(c, in, out);
+            }
+            if (e == hipSuccess) c->cur = 1 - c->cur;
+        }
         if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
-        c->cur = 1 - c->cur;
         ++c->steps;
         if (c->check_every > 0 && c->steps % c->check_every == 0) {
             double tot[5];
@@ -342,10 +365,14 @@ int lbm_memory_info(const lbm_ctx *c, int64_t *state_bytes, int64_t *step_bytes)
 {
     if (!c) return LBM_EINVAL;
     const int64_t per_copy = (int64_t)c->elem * c->state_elems;
+    const int64_t copies = c->scheme == LBM_SCHEME_POPULATION_AA ? 1 : 2;
     if (state_bytes)
-        *state_bytes = 2 * per_copy + (c->scratch_phi ? (int64_t)sizeof(float) * c->N : 0) +
+        *state_bytes = copies * per_copy + (c->scratch_phi ? (int64_t)sizeof(float) * c->N : 0) +
                        (c->scratch_adj ? (int64_t)c->elem * c->lay3.plane * c->nz : 0);
-    if (step_bytes) *step_bytes = 2 * (int64_t)c->elem * c->nfields * c->N;
+    // Split approach: the collision pass reads all stored fields and writes S'
+    // (6 fields), the streaming pass reads and writes all of them.
+    const int64_t moved = c->split ? 3 * (int64_t)c->nfields + 6 : 2 * (int64_t)c->nfields;
+    if (step_bytes) *step_bytes = moved * (int64_t)c->elem * c->N;
     return LBM_OK;
 }
 
@@ -360,6 +387,7 @@ int lbm_save_state(lbm_ctx *c, void *dst)
 {
     if (!c) return LBM_EINVAL;
     if (!dst) return fail(c, LBM_EINVAL, "save_state: NULL buffer");
+    if (c->scheme == LBM_SCHEME_POPULATION_AA) return fail(c, LBM_ESTATE, "save_state: not for the in-place scheme");
     c->err.clear();
     DeviceGuard g(c->device);
     hipError_t e = lbm::launch_copy(c, c->state[c->cur], dst, (int64_t)c->elem * c->state_elems);
@@ -371,6 +399,7 @@ int lbm_load_state(lbm_ctx *c, const void *src)
 {
     if (!c) return LBM_EINVAL;
     if (!src) return fail(c, LBM_EINVAL, "load_state: NULL buffer");
+    if (c->scheme == LBM_SCHEME_POPULATION_AA) return fail(c, LBM_ESTATE, "load_state: not for the in-place scheme");
     c->err.clear();
     DeviceGuard g(c->device);
     hipError_t e = lbm::launch_copy(c, src, c->state[c->cur], (int64_t)c->elem * c->state_elems);
@@ -383,6 +412,7 @@ int lbm_step_state(lbm_ctx *c, const void *src, void *dst)
     if (!c) return LBM_EINVAL;
     if (!src || !dst || src == dst) return fail(c, LBM_EINVAL, "step_state: NULL or identical buffers");
     if (c->scheme != LBM_SCHEME_MOMENT) return fail(c, LBM_ESTATE, "step_state: moment scheme only");
+    if (c->split) return fail(c, LBM_ESTATE, "step_state: fused step only (split context)");
     c->err.clear();
     DeviceGuard g(c->device);
     hipError_t e = c->species == 2 ? lbm::launch_cg_step(c, src, dst) : lbm::launch_moment_step(c, src, dst);

@@ -20,6 +20,10 @@ constexpr int kThreads = 256;
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
+// In-place population scheme after an odd number of steps: arrivals stored
+// reversed at their own node.
+inline bool aa_odd(const lbm_ctx *c) { return c->scheme == LBM_SCHEME_POPULATION_AA && (c->steps & 1); }
+
 // ---- moment scheme -------------------------------------------------------------
 
 // Stored offset of public node n (x fastest) in the blocked moment layout.
@@ -135,10 +139,11 @@ __global__ void k_set_population_state(const T *__restrict__ src, int64_t stride
     }
 }
 
-// Moments of the populations arriving at x, f~_i = A_i[x - c_i].
+// Moments of the populations arriving at x: f~_i = A_i[x - c_i], or, for the
+// in-place scheme after an odd number of steps (odd), f~_i = A_{-i}[x].
 template <int Q, class S, class T>
 __global__ void k_get_population_state(const S *__restrict__ A, T *__restrict__ dst, int64_t stride, int nx,
-                                       int ny, int nz, int64_t N)
+                                       int ny, int nz, int64_t N, bool odd)
 {
     using L = Lattice<Q>;
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -152,7 +157,8 @@ __global__ void k_get_population_state(const S *__restrict__ A, T *__restrict__ 
     for (int i = 0; i < Q; ++i) {
         const int xs = (x - L::cx(i) + nx) % nx, ys = (y - L::cy(i) + ny) % ny, zs = (z - L::cz(i) + nz) % nz;
         const int64_t s = (int64_t)xs + (int64_t)nx * ((int64_t)ys + (int64_t)ny * zs);
-        accumulate<Q, double>(a, (double)Store<S>::load(A[(int64_t)i * N + s]), i);
+        const int64_t at = odd ? (int64_t)opposite<Q>(i) * N + n : (int64_t)i * N + s;
+        accumulate<Q, double>(a, (double)Store<S>::load(A[at]), i);
     }
     const double rho = 1.0 + a.r;
     dst[n] = (T)rho;
@@ -418,10 +424,10 @@ hipError_t launch_get_moments(const lbm_ctx *c, const void *state, void *dst, in
                                        c->stream, A, d, stride, c->nx, c->ny, c->nz, c->N);
             } else if (c->q == 19) {
                 hipLaunchKernelGGL((k_get_population_state<19, S, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0,
-                                   c->stream, st, d, stride, c->nx, c->ny, c->nz, c->N);
+                                   c->stream, st, d, stride, c->nx, c->ny, c->nz, c->N, aa_odd(c));
             } else {
                 hipLaunchKernelGGL((k_get_population_state<27, S, T>), dim3(blocks_for(c->N)), dim3(kThreads), 0,
-                                   c->stream, st, d, stride, c->nx, c->ny, c->nz, c->N);
+                                   c->stream, st, d, stride, c->nx, c->ny, c->nz, c->N, aa_odd(c));
             }
             return hipGetLastError();
         };

@@ -17,6 +17,7 @@ struct lbm_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
     int check_every = 0;
+    int split = 0;    // moment scheme run as the split approach (collision pass + streaming pass)
     int nfields = 0;  // stored arrays per state copy
     size_t elem = 4;  // bytes per stored element
     int64_t state_elems = 0;  // elements per state copy (blocked moment layout or q x N populations)
@@ -36,8 +37,12 @@ namespace lbm {
 
 constexpr int kReduceBlocks = 1024;
 
-// Moment scheme.
-hipError_t launch_moment_step(const lbm_ctx *c, const void *in, void *out);
+// Moment scheme.  collided: `in` holds post-collision moments (split
+// approach), the step only reconstructs, pulls and sums.
+hipError_t launch_moment_step(const lbm_ctx *c, const void *in, void *out, bool collided = false);
+
+// Collision pass of the split approach, in place on the stored state.
+hipError_t launch_moment_collide(const lbm_ctx *c, void *state);
 
 // Moment scheme, two species (colour gradient).
 hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out);
@@ -56,6 +61,10 @@ hipError_t launch_cg_adjoint_step(const lbm_ctx *c, const void *state, const voi
 // Co-state (real type of the context, nfields fields) between the public
 // layout (nfields x N) and the stored blocked layout (state_elems elements).
 hipError_t launch_costate_convert(const lbm_ctx *c, const void *src, void *dst, bool to_stored);
+
+// Population scheme in place (AA pattern) on the single array `state`; odd:
+// the state has gone through an odd number of steps.
+hipError_t launch_population_aa_step(const lbm_ctx *c, void *state, bool odd);
 
 // Population scheme.
 hipError_t launch_population_step(const lbm_ctx *c, const void *in, void *out);

@@ -79,6 +79,27 @@ __device__ __forceinline__ Collided<R> collide(R dr, R jx, R jy, R jz, R sxx, R 
     return p;
 }
 
+// The same record built from moments that are already post-collision (the
+// split approach of Sec. III stores them between its two passes); equal to
+// collide() applied to the pre-collision moments when S' was stored exactly.
+template <class R>
+__device__ __forceinline__ Collided<R> collided_from(R dr, R jx, R jy, R jz, R sxx, R syy, R szz, R sxy, R sxz,
+                                                     R syz)
+{
+    Collided<R> p;
+    p.sxx = sxx;
+    p.syy = syy;
+    p.szz = szz;
+    p.sxy = sxy;
+    p.sxz = sxz;
+    p.syz = syz;
+    p.T = fma_(R(-1.5), (p.sxx + p.syy) + p.szz, dr);
+    p.jx = jx;
+    p.jy = jy;
+    p.jz = jz;
+    return p;
+}
+
 // Shifted population h~_i of direction i written out on its own (used by
 // the conversion kernels; the step kernels use the layered form below).
 template <int Q, class R>

@@ -22,6 +22,11 @@
 // LDS phase of the current plane runs.  Tiles are numbered so that the
 // workgroups an XCD receives (consecutive ids modulo 8) cover a contiguous
 // block of tiles, keeping halo re-reads inside one L2.
+//
+// The paper's split approach (Sec. III) is available for comparison: a
+// node-local collision pass relaxes the stored moments in place, and the
+// tile kernel, instantiated with COLLIDED, then only reconstructs, pulls and
+// sums.  It moves 36 stored values per node instead of 20.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -34,7 +39,7 @@
 namespace lbm {
 namespace {
 
-template <int Q, class S, int TX, int TY>
+template <int Q, class S, int TX, int TY, bool COLLIDED>
 __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in, S *__restrict__ out, TileGrid g,
                                                         typename Store<S>::real omega,
                                                         typename Store<S>::real s_pi,
@@ -98,6 +103,11 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
     };
 
     auto collide_node = [&](const Moments<R> &v) {
+        if constexpr (COLLIDED) {
+            const R sc = kScaled ? inv_s_pi : R(1);
+            return collided_from<R>(v.v[0], v.v[1], v.v[2], v.v[3], v.v[4] * sc, v.v[5] * sc, v.v[6] * sc,
+                                    v.v[7] * sc, v.v[8] * sc, v.v[9] * sc);
+        }
         if (kScaled)
             return collide<R>(v.v[0], v.v[1], v.v[2], v.v[3], v.v[4] * inv_s_pi, v.v[5] * inv_s_pi,
                               v.v[6] * inv_s_pi, v.v[7] * inv_s_pi, v.v[8] * inv_s_pi, v.v[9] * inv_s_pi, omega);
@@ -181,7 +191,47 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
     }
 }
 
-template <int Q, class S, int TX, int TY, int WG_PER_CU>
+// Collision pass of the split approach: (dr, j, S) -> (dr, j, S') in place
+// at every stored node slot (dr and j unchanged, not rewritten).  One thread
+// per slot; the slots of unused block edges hold zeros and stay zero.
+template <class S>
+__global__ __launch_bounds__(256) void k_moment_collide(S *__restrict__ st, int64_t slots,
+                                                        typename Store<S>::real omega,
+                                                        typename Store<S>::real s_pi,
+                                                        typename Store<S>::real inv_s_pi)
+{
+    using R = typename Store<S>::real;
+    constexpr bool kScaled = sizeof(S) == 2;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= slots) return;
+    const int64_t base = (t / kBlock) * (10 * kBlock) + t % kBlock;
+    Moments<R> v;
+    load_moments<S>(st, kBlock, base, v);
+    const R si = kScaled ? inv_s_pi : R(1);
+    const Collided<R> p = collide<R>(v.v[0], v.v[1], v.v[2], v.v[3], v.v[4] * si, v.v[5] * si, v.v[6] * si,
+                                     v.v[7] * si, v.v[8] * si, v.v[9] * si, omega);
+    const R so = kScaled ? s_pi : R(1);
+    store_out(st + base + 4 * kBlock, Store<S>::make(kScaled ? p.sxx * so : p.sxx));
+    store_out(st + base + 5 * kBlock, Store<S>::make(kScaled ? p.syy * so : p.syy));
+    store_out(st + base + 6 * kBlock, Store<S>::make(kScaled ? p.szz * so : p.szz));
+    store_out(st + base + 7 * kBlock, Store<S>::make(kScaled ? p.sxy * so : p.sxy));
+    store_out(st + base + 8 * kBlock, Store<S>::make(kScaled ? p.sxz * so : p.sxz));
+    store_out(st + base + 9 * kBlock, Store<S>::make(kScaled ? p.syz * so : p.syz));
+}
+
+template <class S>
+hipError_t run_collide(const lbm_ctx *c, void *state)
+{
+    using R = typename Store<S>::real;
+    const int64_t slots = c->lay.plane / 10 * c->nz;
+    const int64_t blocks = (slots + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_moment_collide<S>), dim3((unsigned)blocks), dim3(256), 0, c->stream,
+                       static_cast<S *>(state), slots, (R)c->omega, (R)c->s_pi, (R)(1.0 / c->s_pi));
+    return hipGetLastError();
+}
+
+template <int Q, class S, int TX, int TY, int WG_PER_CU, bool COLLIDED>
 hipError_t run(const lbm_ctx *c, const void *in, void *out)
 {
     using R = typename Store<S>::real;
@@ -197,7 +247,7 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out)
     g.chunks = (c->nz + g.zchunk - 1) / g.zchunk;
     const int64_t blocks = (int64_t)g.tiles_x * g.tiles_y * g.chunks;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_moment_tile<Q, S, TX, TY>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
+    hipLaunchKernelGGL((k_moment_tile<Q, S, TX, TY, COLLIDED>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
                        static_cast<const S *>(in), static_cast<S *>(out), g, (R)c->omega, (R)c->s_pi,
                        (R)(1.0 / c->s_pi));
     return hipGetLastError();
@@ -209,30 +259,43 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out)
 // for D3Q27 FP32) measured 3-4 % faster than 64 x 16 tiles (one stored block,
 // 114 KB), despite a halo ring of half the tile; other grids use 64 x 16.
 // FP64 uses 32 x 8 (two per CU), its populations taking twice the LDS.
-template <int Q, class S>
+template <int Q, class S, bool COLLIDED>
 hipError_t run_wide(const lbm_ctx *c, const void *in, void *out)
 {
-    return c->nx % 256 == 0 ? run<Q, S, 256, 4, 1>(c, in, out) : run<Q, S, 64, 16, 1>(c, in, out);
+    return c->nx % 256 == 0 ? run<Q, S, 256, 4, 1, COLLIDED>(c, in, out) : run<Q, S, 64, 16, 1, COLLIDED>(c, in, out);
 }
 
-template <int Q>
+template <int Q, bool COLLIDED>
 hipError_t dispatch_storage(const lbm_ctx *c, const void *in, void *out)
 {
     switch (c->storage) {
-    case LBM_STORE_F64: return run<Q, double, 32, 8, 2>(c, in, out);
-    case LBM_STORE_F32: return run_wide<Q, float>(c, in, out);
-    case LBM_STORE_F16: return run_wide<Q, f16>(c, in, out);
-    case LBM_STORE_BF16: return run_wide<Q, bf16>(c, in, out);
+    case LBM_STORE_F64: return run<Q, double, 32, 8, 2, COLLIDED>(c, in, out);
+    case LBM_STORE_F32: return run_wide<Q, float, COLLIDED>(c, in, out);
+    case LBM_STORE_F16: return run_wide<Q, f16, COLLIDED>(c, in, out);
+    case LBM_STORE_BF16: return run_wide<Q, bf16, COLLIDED>(c, in, out);
     default: return hipErrorInvalidValue;
     }
 }
 
 } // namespace
 
-hipError_t launch_moment_step(const lbm_ctx *c, const void *in, void *out)
+hipError_t launch_moment_step(const lbm_ctx *c, const void *in, void *out, bool collided)
 {
     if (c->species != 1) return hipErrorNotSupported;
-    return c->q == 19 ? dispatch_storage<19>(c, in, out) : dispatch_storage<27>(c, in, out);
+    if (collided) return c->q == 19 ? dispatch_storage<19, true>(c, in, out) : dispatch_storage<27, true>(c, in, out);
+    return c->q == 19 ? dispatch_storage<19, false>(c, in, out) : dispatch_storage<27, false>(c, in, out);
+}
+
+hipError_t launch_moment_collide(const lbm_ctx *c, void *state)
+{
+    if (c->species != 1) return hipErrorNotSupported;
+    switch (c->storage) {
+    case LBM_STORE_F64: return run_collide<double>(c, state);
+    case LBM_STORE_F32: return run_collide<float>(c, state);
+    case LBM_STORE_F16: return run_collide<f16>(c, state);
+    case LBM_STORE_BF16: return run_collide<bf16>(c, state);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 } // namespace lbm

@@ -6,6 +6,16 @@
 // moments (Eqs. 1-3), relaxes towards the equilibrium of Eq. 5 with Eq. 7,
 // and writes its q post-collision populations to the other buffer.
 //
+// One species in place (AA pattern, one copy of the q arrays): slot i of node
+// y holds, after an even number of steps, the post-collision population f*_i
+// of y (the layout of the two-buffer scheme); a step from that state pulls
+// f_i(x) from slot i of x - c_i, collides, and pushes f*_i(x) into the
+// reversed slot of its destination, slot -i of x + c_i; after an odd number of
+// steps slot -i of y therefore holds the population arriving at y, and the
+// next step is node-local (read slot -i of x, write slot i of x).  In the
+// non-local step the slots a node writes are exactly the slots it read
+// ((j, x - c_j) for all j), so the update is race free in place.
+//
 // Two species (standard colour-gradient LB with stored populations): 2q
 // arrays, species 1 then species 2, post-collision.  Each step is two
 // kernels, as in split colour-gradient codes: a density pass that pulls both
@@ -70,6 +80,83 @@ __global__ __launch_bounds__(256) void k_population_pull(const S *__restrict__ i
         const R feq = reconstruct<Q, R>(eq, i);
         out[(int64_t)i * N + n] = Store<S>::make(fma_(omega, feq - f[i], f[i]));
     }
+}
+
+// BGK relaxation of the shifted populations f (in place), Eqs. 5 and 7.
+template <int Q, class R>
+__device__ __forceinline__ void bgk_relax(R *f, R omega)
+{
+    MomentAcc<R> a;
+    a.zero();
+#pragma unroll
+    for (int i = 0; i < Q; ++i) accumulate<Q, R>(a, f[i], i);
+    const R inv_rho = reciprocal<R>(R(1) + a.r);
+    Collided<R> eq;
+    eq.jx = a.jx;
+    eq.jy = a.jy;
+    eq.jz = a.jz;
+    eq.sxx = a.jx * a.jx * inv_rho;
+    eq.syy = a.jy * a.jy * inv_rho;
+    eq.szz = a.jz * a.jz * inv_rho;
+    eq.sxy = a.jx * a.jy * inv_rho;
+    eq.sxz = a.jx * a.jz * inv_rho;
+    eq.syz = a.jy * a.jz * inv_rho;
+    eq.T = a.r - R(1.5) * (eq.sxx + eq.syy + eq.szz);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = fma_(omega, reconstruct<Q, R>(eq, i) - f[i], f[i]);
+}
+
+// One AA step on the single population array A; ODD: the state has gone
+// through an odd number of steps (arrivals stored reversed at their node).
+template <int Q, class S, bool ODD>
+__global__ __launch_bounds__(256) void k_population_aa(S *__restrict__ A, int nx, int ny, int nz, int64_t N,
+                                                       typename Store<S>::real omega)
+{
+    using R = typename Store<S>::real;
+    using L = Lattice<Q>;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int x = (int)(n % nx);
+    const int64_t t = n / nx;
+    const int y = (int)(t % ny);
+    const int z = (int)(t / ny);
+    auto node = [&](int dx, int dy, int dz) -> int64_t {
+        int xs = x + dx, ys = y + dy, zs = z + dz;
+        xs += xs < 0 ? nx : 0;
+        xs -= xs >= nx ? nx : 0;
+        ys += ys < 0 ? ny : 0;
+        ys -= ys >= ny ? ny : 0;
+        zs += zs < 0 ? nz : 0;
+        zs -= zs >= nz ? nz : 0;
+        return (int64_t)xs + (int64_t)nx * ((int64_t)ys + (int64_t)ny * zs);
+    };
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t at = ODD ? (int64_t)opposite<Q>(i) * N + n : (int64_t)i * N + node(-L::cx(i), -L::cy(i), -L::cz(i));
+        f[i] = Store<S>::load(A[at]);
+    }
+    bgk_relax<Q, R>(f, omega);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t at = ODD ? (int64_t)i * N + n : (int64_t)opposite<Q>(i) * N + node(L::cx(i), L::cy(i), L::cz(i));
+        A[at] = Store<S>::make(f[i]);
+    }
+}
+
+template <int Q, class S>
+hipError_t run_aa(const lbm_ctx *c, void *state, bool odd)
+{
+    using R = typename Store<S>::real;
+    const int64_t blocks = (c->N + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    if (odd)
+        hipLaunchKernelGGL((k_population_aa<Q, S, true>), dim3((unsigned)blocks), dim3(256), 0, c->stream,
+                           static_cast<S *>(state), c->nx, c->ny, c->nz, c->N, (R)c->omega);
+    else
+        hipLaunchKernelGGL((k_population_aa<Q, S, false>), dim3((unsigned)blocks), dim3(256), 0, c->stream,
+                           static_cast<S *>(state), c->nx, c->ny, c->nz, c->N, (R)c->omega);
+    return hipGetLastError();
 }
 
 template <int Q, class S>
@@ -215,6 +302,16 @@ hipError_t launch_population_step(const lbm_ctx *c, const void *in, void *out)
     if (c->species != 1) return hipErrorNotSupported;
     if (c->storage == LBM_STORE_F64) return c->q == 19 ? run<19, double>(c, in, out) : run<27, double>(c, in, out);
     if (c->storage == LBM_STORE_F32) return c->q == 19 ? run<19, float>(c, in, out) : run<27, float>(c, in, out);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_population_aa_step(const lbm_ctx *c, void *state, bool odd)
+{
+    if (c->species != 1) return hipErrorNotSupported;
+    if (c->storage == LBM_STORE_F64)
+        return c->q == 19 ? run_aa<19, double>(c, state, odd) : run_aa<27, double>(c, state, odd);
+    if (c->storage == LBM_STORE_F32)
+        return c->q == 19 ? run_aa<19, float>(c, state, odd) : run_aa<27, float>(c, state, odd);
     return hipErrorInvalidValue;
 }
 

@@ -20,12 +20,14 @@ _STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
 class LBM:
     """One periodic box advanced by the moment-only scheme (or, with
-    scheme="population", by the population-storing baseline)."""
+    scheme="population" / "population_aa", by the population-storing
+    baselines with two copies / in place; split=True runs the moment scheme
+    as the paper's split approach, a collision pass and a streaming pass)."""
 
     def __init__(self, shape, lattice: int = 19, tau: float = 0.8, species: int = 1, *,
                  scheme: str = "moment", storage: str = "f32", beta: float = 0.7, sigma: float = 0.01,
                  s_pi: float = 0.0, device: int = 0, stream: torch.cuda.Stream | None = None,
-                 check_every: int = 0):
+                 check_every: int = 0, split: bool = False):
         lib = _lib.load()
         self.nx, self.ny, self.nz = (int(s) for s in shape)
         self.q, self.tau, self.species = int(lattice), float(tau), int(species)
@@ -42,6 +44,7 @@ class LBM:
         opts.stream = ctypes.c_void_p(self.stream.cuda_stream)
         opts.device = device
         opts.check_every = check_every
+        opts.split = int(bool(split))
         ctx = ctypes.c_void_p()
         rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(self.nx, self.ny, self.nz), self.q, self.tau,
                             self.species, ctypes.byref(opts))
@@ -118,7 +121,7 @@ class LBM:
         return np.array(out[:])
 
     def memory_info(self):
-        """(state bytes for both copies, minimum bytes moved per step)."""
+        """(bytes of every stored state copy, minimum bytes moved per step)."""
         a, b = ctypes.c_int64(), ctypes.c_int64()
         _lib.check(self._lib.lbm_memory_info(self._ctx, ctypes.byref(a), ctypes.byref(b)), self._ctx)
         return a.value, b.value

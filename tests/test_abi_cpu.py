@@ -50,6 +50,8 @@ def test_error_strings_and_null_safety():
     ((8, 8, 8), 19, 0.8, 1, 7, 1),     # scheme
     ((8, 8, 8), 19, 0.8, 1, 0, 9),     # storage
     ((8, 8, 8), 19, 0.8, 1, 1, 2),     # population scheme stores F32/F64 only
+    ((8, 8, 8), 19, 0.8, 1, 2, 3),     # in-place population scheme: F32/F64 only
+    ((8, 8, 8), 19, 0.8, 2, 2, 1),     # in-place population scheme: one species
 ])
 def test_create_rejects_bad_arguments_before_device(grid, q, tau, species, scheme, storage):
     lib = _lib.load()
@@ -58,5 +60,23 @@ def test_create_rejects_bad_arguments_before_device(grid, q, tau, species, schem
     opts.scheme, opts.storage = scheme, storage
     ctx = ctypes.c_void_p(123)
     rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(*grid), q, tau, species, ctypes.byref(opts))
+    assert rc == _lib.LBM_EINVAL
+    assert not ctx.value
+
+
+@pytest.mark.parametrize("species,scheme,split", [
+    (1, 0, 2),     # split is 0 or 1
+    (2, 0, 1),     # split approach: one species
+    (1, 1, 1),     # split approach: moment scheme only
+    (1, 2, 1),
+])
+def test_create_rejects_bad_split_before_device(species, scheme, split):
+    lib = _lib.load()
+    opts = _lib.Opts()
+    lib.lbm_default_opts(ctypes.byref(opts))
+    assert opts.split == 0
+    opts.scheme, opts.split = scheme, split
+    ctx = ctypes.c_void_p(123)
+    rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(8, 8, 8), 19, 0.8, species, ctypes.byref(opts))
     assert rc == _lib.LBM_EINVAL
     assert not ctx.value

@@ -187,6 +187,66 @@ def test_population_scheme_matches_oracle(LBM, oracle, q, storage, tol):
     assert np.abs(got - ref).max() <= tol
 
 
+# In place (AA pattern): one copy of the populations, steps alternate between a
+# neighbour-access and a node-local update; odd and even step counts end in
+# different storage orders, both read back through the same moments.
+@pytest.mark.parametrize("steps", [7, 8])
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-6)])
+def test_population_inplace_matches_oracle(LBM, oracle, q, storage, tol, steps):
+    shape = (11, 13, 17)
+    _say(f"in-place population scheme {shape} D3Q{q} {storage} {steps} steps")
+    H = I.random_moments(shape, seed=50 + q)
+    f = oracle.populations_from_moments(H, q)
+    ref = oracle.moments_from_populations(oracle.population_run(f, q, 0.7, steps), q)
+    got = _gpu_run_from_moments(LBM, H, q, 0.7, steps, storage=storage, scheme="population_aa")
+    assert np.abs(got - ref).max() <= tol
+
+
+@pytest.mark.parametrize("steps", [0, 1, 2, 5])
+def test_population_inplace_totals_and_memory(LBM, steps):
+    """Totals (momentum sign at odd parity included) against the two-copy
+    scheme; one copy of q arrays held."""
+    shape = (9, 10, 12)
+    _say(f"in-place population totals {shape} {steps} steps")
+    H = I.random_moments(shape, seed=61)
+    tot, mem = {}, {}
+    for scheme in ("population", "population_aa"):
+        sim = LBM(shape[::-1], 19, 0.8, storage="f64", scheme=scheme)
+        sim.set_moments(torch.from_numpy(H).cuda())
+        sim.step(steps)
+        tot[scheme] = sim.reduce()
+        mem[scheme] = sim.memory_info()
+        assert sim.steps_done == steps
+        sim.close()
+    N = int(np.prod(shape))
+    assert np.abs(tot["population"] - tot["population_aa"]).max() <= 1e-10 * N
+    assert np.abs(tot["population_aa"][2:] - H[1:4].sum(axis=(1, 2, 3))).max() <= 1e-10 * N
+    assert mem["population_aa"][0] == 19 * 8 * N
+    assert mem["population"][0] == 2 * 19 * 8 * N
+    assert mem["population_aa"][1] == mem["population"][1]
+
+
+def test_population_inplace_minimum_box_and_state_calls(LBM, oracle):
+    from paper_2301_01622_amd import _lib
+    H = I.random_moments((3, 3, 3), seed=62)
+    f = oracle.populations_from_moments(H, 27)
+    ref = oracle.moments_from_populations(oracle.population_run(f, 27, 0.9, 5), 27)
+    sim = LBM((3, 3, 3), 27, 0.9, storage="f64", scheme="population_aa")
+    sim.set_moments(torch.from_numpy(H).cuda())
+    sim.step(5)
+    got = sim.get_moments(torch.float64).cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-12
+    buf = torch.empty(sim.state_bytes, dtype=torch.uint8, device="cuda")
+    with pytest.raises(_lib.LbmError) as e:
+        sim.save_state(buf)
+    assert e.value.code == _lib.LBM_ESTATE
+    with pytest.raises(_lib.LbmError) as e:
+        sim.load_state(buf)
+    assert e.value.code == _lib.LBM_ESTATE
+    sim.close()
+
+
 # ---- state handling --------------------------------------------------------------------
 
 @pytest.mark.parametrize("storage,tol", [("f64", 0.0), ("f32", 1e-7), ("bf16", 1e-2), ("f16", 2e-3)])
