@@ -98,6 +98,13 @@ typedef struct {
                         (else LBM_EINVAL); results equal the fused step's bit for bit with
                         FP32/FP64 storage (16-bit storage rounds the stored S'); 36 instead of
                         20 stored values moved per node; lbm_step_state gives LBM_ESTATE */
+    int steps_per_sweep; /* time steps lbm_step applies per pass over the state: 1, or 2 (two
+                        steps carried through each tile in one pass, the state read and written
+                        once per two steps; results equal single steps bit for bit).  2 needs
+                        one species, the moment scheme, the fused step and FP32/FP16/BF16
+                        storage (else LBM_EINVAL).  0 (default): 2 where available, else 1.
+                        lbm_step falls back to single steps for an odd remainder and where
+                        a check_every health check falls between the two steps */
 } lbm_opts;
 
 /* Caller-owned moment buffers, see the layout above. */

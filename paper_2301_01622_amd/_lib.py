@@ -39,6 +39,7 @@ class Opts(ctypes.Structure):
         ("device", ctypes.c_int),
         ("check_every", ctypes.c_int),
         ("split", ctypes.c_int),
+        ("steps_per_sweep", ctypes.c_int),
     ]
 
 

@@ -102,6 +102,7 @@ void lbm_default_opts(lbm_opts *o)
     o->device = -1;
     o->check_every = 0;
     o->split = 0;
+    o->steps_per_sweep = 0;
 }
 
 const char *lbm_strerror(int code)
@@ -145,6 +146,10 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     if (!(o.s_pi >= 0.0) || !std::isfinite(o.s_pi)) return LBM_EINVAL;
     if (species == 2 && o.scheme == LBM_SCHEME_POPULATION && o.storage != LBM_STORE_F32) return LBM_EINVAL;
 
+    // Two-step sweeps: one species, fused moment step, not FP64 storage.
+    const bool sweep2_ok = o.scheme == LBM_SCHEME_MOMENT && species == 1 && o.split == 0 && o.storage != LBM_STORE_F64;
+    if (o.steps_per_sweep < 0 || o.steps_per_sweep > 2 || (o.steps_per_sweep == 2 && !sweep2_ok)) return LBM_EINVAL;
+    const int sweep = o.steps_per_sweep == 0 ? (sweep2_ok ? 2 : 1) : o.steps_per_sweep;
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
     if (!c) return LBM_ENOMEM;
     c->nx = grid.nx;
@@ -164,6 +169,7 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     c->stream = static_cast<hipStream_t>(o.stream);
     c->check_every = o.check_every;
     c->split = o.split;
+    c->sweep = sweep;
     c->elem = storage_bytes(o.storage);
     c->nfields = o.scheme == LBM_SCHEME_MOMENT ? (species == 1 ? 10 : 11) : lattice * species;
     c->lay = lbm::moment_layout(c->nx, c->ny, c->nfields);
@@ -332,9 +338,16 @@ int lbm_step(lbm_ctx *c, int n)
     if (!c || n < 0) return fail(c, LBM_EINVAL, "lbm_step: bad argument");
     c->err.clear();
     DeviceGuard g(c->device);
-    for (int t = 0; t < n; ++t) {
+    for (int t = 0; t < n;) {
         hipError_t e;
-        if (c->scheme == LBM_SCHEME_POPULATION_AA) {
+        int done = 1;
+        // A two-step sweep unless a health check falls after its first step.
+        const bool two = c->sweep == 2 && n - t >= 2 && !(c->check_every > 0 && (c->steps + 1) % c->check_every == 0);
+        if (two) {
+            e = lbm::launch_moment_sweep2(c, c->state[c->cur], c->state[1 - c->cur]);
+            if (e == hipSuccess) c->cur = 1 - c->cur;
+            done = 2;
+        } else if (c->scheme == LBM_SCHEME_POPULATION_AA) {
             e = lbm::launch_population_aa_step(c, c->state[0], (c->steps & 1) != 0);
         } else {
             const void *in = c->state[c->cur];
@@ -351,7 +364,8 @@ int lbm_step(lbm_ctx *c, int n)
             if (e == hipSuccess) c->cur = 1 - c->cur;
         }
         if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
-        ++c->steps;
+        c->steps += done;
+        t += done;
         if (c->check_every > 0 && c->steps % c->check_every == 0) {
             double tot[5];
             int rc = lbm_reduce(c, tot);

@@ -18,6 +18,7 @@ struct lbm_ctx {
     int device = 0;
     int check_every = 0;
     int split = 0;    // moment scheme run as the split approach (collision pass + streaming pass)
+    int sweep = 1;    // time steps per pass over the state (1, or 2: two-step sweeps)
     int nfields = 0;  // stored arrays per state copy
     size_t elem = 4;  // bytes per stored element
     int64_t state_elems = 0;  // elements per state copy (blocked moment layout or q x N populations)
@@ -43,6 +44,11 @@ hipError_t launch_moment_step(const lbm_ctx *c, const void *in, void *out, bool 
 
 // Collision pass of the split approach, in place on the stored state.
 hipError_t launch_moment_collide(const lbm_ctx *c, void *state);
+
+// Two moment steps in one pass over the state (one species, fused step,
+// FP32/FP16/BF16 storage); equal to two launch_moment_step calls bit for bit.
+bool moment_sweep2_supported(const lbm_ctx *c);
+hipError_t launch_moment_sweep2(const lbm_ctx *c, const void *in, void *out);
 
 // Moment scheme, two species (colour gradient).
 hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out);

@@ -1,0 +1,276 @@
+// Two time steps per sweep of the moment-only scheme (one species),
+// LDS-tiled for gfx950.
+//
+// The single step reads every stored moment once and writes it once, 80 B
+// per node and step at FP32, and HBM bandwidth bounds it.  Here a workgroup
+// carries its tile through two consecutive steps (Sec. II-III, Eqs. 4-9,
+// applied twice) while it marches along z, so the state crosses HBM once per
+// two steps:
+//
+//   * source region R0 = interior tile plus a two-node ring: each node loads
+//     its 10 moments of plane p, collides them and writes its q populations
+//     to LDS buffer P0;
+//   * region R1 = interior plus a one-node ring: each node pulls the
+//     populations of plane p from P0 into three accumulator planes (p-1, p,
+//     p+1).  Plane p-1 of the intermediate state is then complete; it is
+//     rounded to the storage format exactly as a stored state would be,
+//     collided, and its populations are written to LDS buffer P1;
+//   * interior nodes pull from P1 into three more accumulator planes; plane
+//     p-2 of the second step is then complete and is stored.
+//
+// Threads are assigned per role (thread t holds node t of R0, of R1 and of
+// the interior, each numbered row by row), so the active threads of each
+// phase fill whole waves.  Each node of R1 and of the interior computes exactly the
+// arithmetic of the single step (the same collision, reconstruction and
+// layer sums, FMAs explicit), so a sweep equals two single steps bit for bit.
+// The cost is the redundant work on the two rings (R0 and R1 are 1.59x and
+// 1.29x the interior of a 64 x 8 tile): the sweep is bound by arithmetic and
+// LDS rather than HBM (without any global access it still takes 80 % of its
+// time).
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "internal.hpp"
+#include "moment_math.hpp"
+#include "storage.hpp"
+#include "tile_common.hpp"
+
+namespace lbm {
+namespace {
+
+// LDS slot of direction (layer cz, slot sl = (cx+1) + 3 (cy+1)) among the q
+// directions of the lattice, own column included; -1 if absent.
+template <int Q>
+__host__ __device__ constexpr int dir_slot(int cz, int sl)
+{
+    int k = 0;
+    for (int z = -1; z <= 1; ++z)
+        for (int s = 0; s < 9; ++s) {
+            if (!has_dir<Q>(s % 3 - 1, s / 3 - 1, z)) continue;
+            if (z == cz && s == sl) return k;
+            ++k;
+        }
+    return -1;
+}
+
+template <int IX, int IY>
+constexpr int kSweepThreads = ((IX + 4) * (IY + 4) + 63) / 64 * 64;
+
+template <int Q, class S, int IX, int IY>
+__global__ __launch_bounds__((kSweepThreads<IX, IY>)) void k_moment_sweep2(const S *__restrict__ in,
+                                                                        S *__restrict__ out, TileGrid g,
+                                                                        typename Store<S>::real omega,
+                                                                        typename Store<S>::real s_pi,
+                                                                        typename Store<S>::real inv_s_pi)
+{
+    using R = typename Store<S>::real;
+    constexpr bool kScaled = sizeof(S) == 2;  // 16-bit storage keeps S * s_pi
+    constexpr int HX0 = IX + 4, N0 = HX0 * (IY + 4);  // R0: sources of the first step
+    constexpr int HX1 = IX + 2, N1 = HX1 * (IY + 2);  // R1: results of the first step
+    constexpr int NI = IX * IY;
+    __shared__ R p0[Q * N0];
+    __shared__ R p1[Q * N1];
+
+    const int b = xcd_tile_id();
+    const int tx = b % g.tiles_x;
+    const int ty = (b / g.tiles_x) % g.tiles_y;
+    const int chunk = b / (g.tiles_x * g.tiles_y);
+    const int x0 = tx * IX, y0 = ty * IY;
+    const int z0 = chunk * g.zchunk;
+    const int z_end = min(z0 + g.zchunk, g.nz);
+    const int64_t plane = g.lay.plane;
+
+    const int tid = threadIdx.x;
+    const bool r0 = tid < N0, r1 = tid < N1, ri = tid < NI;
+    const int h0 = tid;                                               // slot in P0
+    const int h1x = tid % HX1, h1y = tid / HX1;
+    const int h1in0 = (h1y + 1) * HX0 + (h1x + 1);                    // R1 node's slot in P0
+    const int h1 = tid;                                               // slot in P1
+    const int ix = tid % IX, iy = tid / IX;
+    const int hiin1 = (iy + 1) * HX1 + (ix + 1);                      // interior node's slot in P1
+    const bool active = ri && (x0 + ix < g.nx) && (y0 + iy < g.ny);
+    const int64_t src_xy = r0 ? g.lay.xy(wrap_coord(x0 - 2 + tid % HX0, g.nx), wrap_coord(y0 - 2 + tid / HX0, g.ny))
+                              : 0;
+    const int64_t dst_xy = active ? g.lay.xy(x0 + ix, y0 + iy) : 0;
+
+    MomentAcc<R> a1[3], a2[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        a1[k].zero();
+        a2[k].zero();
+    }
+
+    Moments<R> m_a, m_b;  // moments of source planes p and p+1 (loads in flight)
+    auto fetch = [&](int p, Moments<R> &m) {
+        if (!r0) return;
+        const int zs = p < 0 ? p + g.nz : (p >= g.nz ? p - g.nz : p);
+        load_moments<S>(in, kBlock, src_xy + (int64_t)zs * plane, m);
+    };
+
+    auto collide_node = [&](const Moments<R> &v) {
+        if (kScaled)
+            return collide<R>(v.v[0], v.v[1], v.v[2], v.v[3], v.v[4] * inv_s_pi, v.v[5] * inv_s_pi,
+                              v.v[6] * inv_s_pi, v.v[7] * inv_s_pi, v.v[8] * inv_s_pi, v.v[9] * inv_s_pi, omega);
+        return collide<R>(v.v[0], v.v[1], v.v[2], v.v[3], v.v[4], v.v[5], v.v[6], v.v[7], v.v[8], v.v[9], omega);
+    };
+
+    // The 10 values a finished accumulator is stored as (stored format).
+    auto stored_values = [&](const MomentAcc<R> &a, S *v) {
+        const R m3 = R(-1.0 / 3.0);
+        const R sc = kScaled ? s_pi : R(1);
+        v[0] = Store<S>::make(a.r);
+        v[1] = Store<S>::make(a.jx);
+        v[2] = Store<S>::make(a.jy);
+        v[3] = Store<S>::make(a.jz);
+        v[4] = Store<S>::make(kScaled ? fma_(m3, a.r, a.mxx) * sc : fma_(m3, a.r, a.mxx));
+        v[5] = Store<S>::make(kScaled ? fma_(m3, a.r, a.myy) * sc : fma_(m3, a.r, a.myy));
+        v[6] = Store<S>::make(kScaled ? fma_(m3, a.r, a.mzz) * sc : fma_(m3, a.r, a.mzz));
+        v[7] = Store<S>::make(kScaled ? a.mxy * sc : a.mxy);
+        v[8] = Store<S>::make(kScaled ? a.mxz * sc : a.mxz);
+        v[9] = Store<S>::make(kScaled ? a.myz * sc : a.myz);
+    };
+
+    auto publish = [&](const Collided<R> &c, R *P, int n, int h) {
+        Layer<R> L0, L1, L2;
+        reconstruct_layer<Q, -1, R>(c, L0);
+        reconstruct_layer<Q, 0, R>(c, L1);
+        reconstruct_layer<Q, 1, R>(c, L2);
+#pragma unroll
+        for (int sl = 0; sl < 9; ++sl) {
+            if (dir_slot<Q>(-1, sl) >= 0) P[dir_slot<Q>(-1, sl) * n + h] = L0.v[sl];
+            if (dir_slot<Q>(0, sl) >= 0) P[dir_slot<Q>(0, sl) * n + h] = L1.v[sl];
+            if (dir_slot<Q>(1, sl) >= 0) P[dir_slot<Q>(1, sl) * n + h] = L2.v[sl];
+        }
+    };
+
+    // Layer CZ of the populations streaming into slot h of a buffer of n
+    // slots, rows of hx, added to acc.
+    auto pull_layer = [&](auto czc, const R *P, int n, int hx, int h, MomentAcc<R> &acc) {
+        constexpr int CZ = decltype(czc)::value;
+        Layer<R> f;
+#pragma unroll
+        for (int sl = 0; sl < 9; ++sl) {
+            const int cx = sl % 3 - 1, cy = sl / 3 - 1;
+            f.v[sl] = R(0);
+            if (dir_slot<Q>(CZ, sl) >= 0) f.v[sl] = P[dir_slot<Q>(CZ, sl) * n + h - cy * hx - cx];
+        }
+        accumulate_layer<Q, CZ, R>(acc, f);
+    };
+
+    // One source plane p: first-step populations of p, intermediate plane
+    // p-1, second-step plane p-2.
+    auto plane_step = [&](int p, Moments<R> &m) {
+        if (r0) publish(collide_node(m), p0, N0, h0);
+        __syncthreads();
+        if (p + 2 <= z_end + 1) fetch(p + 2, m);
+
+        if (r1) {
+            pull_layer(std::integral_constant<int, -1>(), p0, N0, HX0, h1in0, a1[0]);
+            pull_layer(std::integral_constant<int, 0>(), p0, N0, HX0, h1in0, a1[1]);
+            pull_layer(std::integral_constant<int, 1>(), p0, N0, HX0, h1in0, a1[2]);
+            // Intermediate plane p-1 has received from p-2, p-1 and p.
+            if (p >= z0) {
+                S v[10];
+                stored_values(a1[0], v);
+                Moments<R> mi;
+#pragma unroll
+                for (int k = 0; k < 10; ++k) mi.v[k] = Store<S>::load(v[k]);
+                publish(collide_node(mi), p1, N1, h1);
+            }
+            a1[0] = a1[1];
+            a1[1] = a1[2];
+            a1[2].zero();
+        }
+        __syncthreads();
+
+        if (p >= z0 && ri) {
+            pull_layer(std::integral_constant<int, -1>(), p1, N1, HX1, hiin1, a2[0]);
+            pull_layer(std::integral_constant<int, 0>(), p1, N1, HX1, hiin1, a2[1]);
+            pull_layer(std::integral_constant<int, 1>(), p1, N1, HX1, hiin1, a2[2]);
+            // Second-step plane p-2 has received from intermediate planes p-3, p-2, p-1.
+            const int d = p - 2;
+            if (d >= z0 && active) {
+                S v[10];
+                stored_values(a2[0], v);
+                const int64_t o = dst_xy + (int64_t)d * plane;
+#pragma unroll
+                for (int k = 0; k < 10; ++k) store_out(out + k * kBlock + o, v[k]);
+            }
+            a2[0] = a2[1];
+            a2[1] = a2[2];
+            a2[2].zero();
+        }
+    };
+
+    // Source planes z0-2 .. z_end+1 feed second-step planes z0 .. z_end-1.
+    fetch(z0 - 2, m_a);
+    fetch(z0 - 1, m_b);
+    for (int p = z0 - 2; p <= z_end + 1; p += 2) {
+        plane_step(p, m_a);
+        if (p + 1 <= z_end + 1) plane_step(p + 1, m_b);
+    }
+}
+
+#ifndef LBM_SWEEP_WG
+#define LBM_SWEEP_WG 1
+#endif
+
+template <int Q, class S, int IX, int IY>
+hipError_t run(const lbm_ctx *c, const void *in, void *out)
+{
+    using R = typename Store<S>::real;
+    TileGrid g;
+    g.nx = c->nx;
+    g.ny = c->ny;
+    g.nz = c->nz;
+    g.N = c->N;
+    g.lay = c->lay;
+    g.tiles_x = (c->nx + IX - 1) / IX;
+    g.tiles_y = (c->ny + IY - 1) / IY;
+    g.zchunk = choose_zchunk(c->nz, g.tiles_x * g.tiles_y, 256 * LBM_SWEEP_WG);
+    g.chunks = (c->nz + g.zchunk - 1) / g.zchunk;
+    const int64_t blocks = (int64_t)g.tiles_x * g.tiles_y * g.chunks;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_moment_sweep2<Q, S, IX, IY>), dim3((unsigned)blocks), dim3(kSweepThreads<IX, IY>), 0,
+                       c->stream, static_cast<const S *>(in), static_cast<S *>(out), g, (R)c->omega, (R)c->s_pi,
+                       (R)(1.0 / c->s_pi));
+    return hipGetLastError();
+}
+
+// Interior tile 64 x 8: full 64-node rows of the stored blocks, 832 threads,
+// 159 KB of LDS for D3Q27 FP32 (the largest 64-wide tile that fits).
+// Measured on 256^3 D3Q27 FP32: 92 GLUPS, against 84 for 32 x 16 tiles and
+// 65 for 16 x 16 (two workgroups per CU) or 64 x 4.
+#ifndef LBM_SWEEP_IX
+#define LBM_SWEEP_IX 64
+#endif
+#ifndef LBM_SWEEP_IY
+#define LBM_SWEEP_IY 8
+#endif
+
+template <int Q>
+hipError_t dispatch_storage(const lbm_ctx *c, const void *in, void *out)
+{
+    switch (c->storage) {
+    case LBM_STORE_F32: return run<Q, float, LBM_SWEEP_IX, LBM_SWEEP_IY>(c, in, out);
+    case LBM_STORE_F16: return run<Q, f16, LBM_SWEEP_IX, LBM_SWEEP_IY>(c, in, out);
+    case LBM_STORE_BF16: return run<Q, bf16, LBM_SWEEP_IX, LBM_SWEEP_IY>(c, in, out);
+    default: return hipErrorNotSupported;
+    }
+}
+
+} // namespace
+
+bool moment_sweep2_supported(const lbm_ctx *c)
+{
+    return c->scheme == LBM_SCHEME_MOMENT && c->species == 1 && !c->split && c->storage != LBM_STORE_F64;
+}
+
+hipError_t launch_moment_sweep2(const lbm_ctx *c, const void *in, void *out)
+{
+    if (!moment_sweep2_supported(c)) return hipErrorNotSupported;
+    return c->q == 19 ? dispatch_storage<19>(c, in, out) : dispatch_storage<27>(c, in, out);
+}
+
+} // namespace lbm

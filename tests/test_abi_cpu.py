@@ -80,3 +80,23 @@ def test_create_rejects_bad_split_before_device(species, scheme, split):
     rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(8, 8, 8), 19, 0.8, species, ctypes.byref(opts))
     assert rc == _lib.LBM_EINVAL
     assert not ctx.value
+
+
+@pytest.mark.parametrize("species,scheme,storage,split,sweep", [
+    (1, 0, 1, 0, 3),     # 0, 1 or 2
+    (1, 0, 1, 0, -1),
+    (1, 0, 0, 0, 2),     # two-step sweeps: not with FP64 storage
+    (2, 0, 1, 0, 2),     # one species only
+    (1, 1, 1, 0, 2),     # moment scheme only
+    (1, 0, 1, 1, 2),     # fused step only
+])
+def test_create_rejects_bad_sweep_before_device(species, scheme, storage, split, sweep):
+    lib = _lib.load()
+    opts = _lib.Opts()
+    lib.lbm_default_opts(ctypes.byref(opts))
+    assert opts.steps_per_sweep == 0
+    opts.scheme, opts.storage, opts.split, opts.steps_per_sweep = scheme, storage, split, sweep
+    ctx = ctypes.c_void_p(123)
+    rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(8, 8, 8), 19, 0.8, species, ctypes.byref(opts))
+    assert rc == _lib.LBM_EINVAL
+    assert not ctx.value

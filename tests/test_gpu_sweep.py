@@ -1,0 +1,91 @@
+"""Two time steps per pass over the state (one species, fused step): the
+sweep kernel carries each tile through two steps with the same per-node
+arithmetic as the single step, so its results must equal single steps bit
+for bit (16-bit storage included: the intermediate state is rounded to the
+storage format as a stored state would be), and match the FP64 oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2301_01622_amd import inputs as I  # noqa: E402
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def _run(H, q, tau, steps, storage, sweep, check_every=0, chunks=(None,)):
+    from paper_2301_01622_amd.lbm import LBM
+    nf, nz, ny, nx = H.shape
+    sim = LBM((nx, ny, nz), q, tau, storage=storage, steps_per_sweep=sweep, check_every=check_every)
+    sim.set_moments(torch.from_numpy(H).cuda())
+    for c in chunks:
+        sim.step(steps if c is None else c)
+    out = sim.get_moments(torch.float64).cpu().numpy()
+    assert sim.steps_done == steps
+    sim.close()
+    return out
+
+
+# (nx, ny, nz): several 32 x 16 tiles with ragged tails and two z-chunks;
+# one tile wider than the box (x-halo wraps onto the tile); minimum box;
+# a 256-wide box.
+SHAPES = [(70, 37, 20), (17, 13, 11), (3, 3, 3), (256, 5, 6)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_sweep_equals_single_steps(shape, q, storage):
+    steps = 7  # three sweeps and one single step
+    _say(f"two-step sweep {shape} D3Q{q} {storage} {steps} steps")
+    H = I.random_moments(shape[::-1], seed=90 + q)
+    a = _run(H, q, 0.62, steps, storage, 2)
+    b = _run(H, q, 0.62, steps, storage, 1)
+    np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_sweep_matches_oracle(oracle, q):
+    shape = (70, 37, 20)
+    _say(f"two-step sweep {shape} D3Q{q} f32 8 steps vs oracle")
+    H = I.random_moments(shape[::-1], seed=95 + q)
+    got = _run(H, q, 0.7, 8, "f32", 2)
+    ref = oracle.moment_run(H, q, 0.7, 8)
+    assert np.abs(got - ref).max() <= 1e-6
+
+
+def test_sweep_with_health_checks_and_split_calls():
+    """check_every = 3 forces single steps where a check falls between the two
+    steps of a sweep; calls of odd length leave single steps too; the result
+    is the same."""
+    H = I.random_moments((20, 37, 70), seed=97)
+    ref = _run(H, 27, 0.6, 12, "f32", 1)
+    np.testing.assert_array_equal(_run(H, 27, 0.6, 12, "f32", 2, check_every=3), ref)
+    np.testing.assert_array_equal(_run(H, 27, 0.6, 12, "f32", 2, chunks=(1, 3, 5, 2, 1)), ref)
+
+
+def test_sweep_full_size_sampled(oracle):
+    """256^3 D3Q27 FP32 (the throughput workload), 2 steps as one sweep,
+    against the oracle on sampled nodes (each from its 5^3 dependency cone)."""
+    n, q, tau, steps = 256, 27, 0.6, 2
+    rho, u = I.random_solenoidal_box(n, I.SEED_C2, umax=1e-3)
+    H0 = oracle.equilibrium_moments(rho, u)
+    from paper_2301_01622_amd.lbm import LBM
+    sim = LBM((n, n, n), q, tau, storage="f32", steps_per_sweep=2)
+    sim.set_moments(torch.from_numpy(H0).cuda())
+    sim.step(steps)
+    got = sim.get_moments(torch.float64).cpu().numpy()
+    sim.close()
+    rng = np.random.default_rng(5)
+    nodes = [(0, 0, 0), (255, 255, 255), (128, 31, 32)] + [tuple(rng.integers(0, n, 3)) for _ in range(5)]
+    r = steps
+    for (z, y, x) in nodes:
+        idx = [np.arange(c - r, c + r + 1) % n for c in (z, y, x)]
+        cube = H0[:, idx[0]][:, :, idx[1]][:, :, :, idx[2]]
+        # The cone is not periodic: only its centre is exact after `steps` steps.
+        ref = oracle.moment_run(np.ascontiguousarray(cube), q, tau, steps)[:, r, r, r]
+        assert np.abs(got[:, z, y, x] - ref).max() <= 1e-6, (z, y, x)
