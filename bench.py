@@ -96,25 +96,46 @@ def adjoint_cost(sim, stream, steps: int, fwd_ms: float, algo_bytes: int = 120,
     g = torch.Generator(device="cuda")
     g.manual_seed(7)
     pub = torch.randn((sim.nfields,) + sim.shape, generator=g, device="cuda", dtype=sim.real_dtype)
-    # the rollout's path: co-states in the library's stored layout
+    # the rollout's path: co-states in the library's stored layout; where the
+    # context runs two-step sweeps the rollout recomputes and reverses pairs
+    # of steps in one pass each
     lam, lam_b = sim.new_costate(), sim.new_costate()
     sim.costate_to_stored(pub, lam)
     dtau = torch.zeros(1, dtype=torch.float64, device="cuda")
+    pairs = getattr(sim, "sweeps", False)
+    if pairs:
+        st1, slot2 = sim.new_checkpoint(), sim.new_checkpoint()
+        sim.step_state(st, st1)
+
+    def adjoint_call():
+        if pairs:
+            sim.adjoint_step2_stored(st1, st, lam, lam_b, dtau)
+        else:
+            sim.adjoint_step_stored(st, lam, lam_b, dtau)
+
+    def recompute_call():
+        if pairs:
+            sim.step_state2(st, slot, slot2)
+        else:
+            sim.step_state(st, slot)
+
+    per = 2 if pairs else 1
+    calls = max(steps // per, 5)
     for _ in range(3):
-        sim.adjoint_step_stored(st, lam, lam_b, dtau)
-        sim.step_state(st, slot)
+        adjoint_call()
+        recompute_call()
     torch.cuda.synchronize()
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     e[0].record(stream)
-    for _ in range(steps):
-        sim.adjoint_step_stored(st, lam, lam_b, dtau)
+    for _ in range(calls):
+        adjoint_call()
     e[1].record(stream)
-    for _ in range(steps):
-        sim.step_state(st, slot)
+    for _ in range(calls):
+        recompute_call()
     e[2].record(stream)
     torch.cuda.synchronize()
-    adj = e[0].elapsed_time(e[1]) / steps
-    rec = e[1].elapsed_time(e[2]) / steps
+    adj = e[0].elapsed_time(e[1]) / (calls * per)
+    rec = e[1].elapsed_time(e[2]) / (calls * per)
     N = sim.n_nodes
     extra = {}
     if single_ms:
@@ -122,6 +143,7 @@ def adjoint_cost(sim, stream, steps: int, fwd_ms: float, algo_bytes: int = 120,
                  "adjoint_plus_recompute_over_single_step_kernel": round((adj + rec) / single_ms, 3)}
     return {
         **extra,
+        "steps_per_call": per,
         "ms_forward_step": round(fwd_ms, 5),
         "ms_adjoint_step": round(adj, 5),
         "ms_recompute_step": round(rec, 5),
@@ -221,7 +243,11 @@ def main() -> int:
         sim.set_equilibrium(rho_d, u_d)
         ms = time_steps(sim, stream, args.steps, args.warmup)
         state_bytes, step_bytes = sim.memory_info()
-        adjoint = adjoint_cost(sim, stream, max(args.steps // 4, 10), ms, single_ms=ms1)
+        adjoint = adjoint_cost(sim, stream, max(args.steps // 4, 10), ms, single_ms=ms1,
+                               note="one species, same 256^3 D3Q27 FP32 box; the rollout's path: two adjoint steps "
+                                    "per call (lbm_adjoint_step2_stored) and two recomputed states per call "
+                                    "(lbm_step_state2); algorithmic bytes of one adjoint step 120 B/node (the "
+                                    "two-step pass moves 80 B/node and step)")
         copy = None
         if args.calibrate_copy > 0:
             buf = sim.new_checkpoint()

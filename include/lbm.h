@@ -204,6 +204,16 @@ int lbm_load_state(lbm_ctx *ctx, const void *src_device);
  * Errors: LBM_EINVAL, LBM_ESTATE (population scheme), LBM_EDEVICE. */
 int lbm_step_state(lbm_ctx *ctx, const void *src_state, void *dst_state);
 
+/* Two time steps from a saved state in one pass (the two-step sweep of
+ * lbm_step): mid_state receives the state after the first step, dst_state the
+ * state after the second, both bit for bit as two lbm_step_state calls would
+ * give them.  Three device buffers of lbm_state_bytes() bytes, pairwise
+ * distinct, must not overlap; the context's own state is not touched.
+ * Recomputes two states of a checkpointed segment for the cost of about one.
+ * Errors: LBM_EINVAL (NULL or aliased), LBM_ESTATE (not one species with
+ * the fused moment step and FP32/FP16/BF16 storage), LBM_EDEVICE. */
+int lbm_step_state2(lbm_ctx *ctx, const void *src_state, void *mid_state, void *dst_state);
+
 /* One reverse step of the discrete adjoint of the moment scheme: the exact
  * transpose of the Jacobian of one step (one species: Eqs. 4-9 and 1-3; two
  * species: the colour-gradient step of Sec. III.A with the perturbation and
@@ -238,6 +248,19 @@ int lbm_adjoint_step(lbm_ctx *ctx, const void *state_t, const void *lam_next, vo
  * lbm_adjoint_step. */
 int lbm_adjoint_step_stored(lbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out,
                             double *dtau_accum);
+
+/* Two reverse steps in one pass, co-states in the stored layout:
+ * lam_out = J(state_t0)^T J(state_t1)^T lam_next, where state_t1 is the state
+ * one step after state_t0 (both in the format of lbm_save_state), i.e. the
+ * same as lbm_adjoint_step_stored(state_t1, lam_next, tmp) followed by
+ * lbm_adjoint_step_stored(state_t0, tmp, lam_out), bit for bit in lam_out.
+ * dtau_accum (device double or NULL) receives the sum of both steps'
+ * contributions (equal to the two single steps' up to FP64 rounding of the
+ * grouping).  One species, fused moment step, FP32/FP16/BF16 storage.
+ * Errors: LBM_EINVAL (NULL, or lam_next aliasing lam_out), LBM_ESTATE,
+ * LBM_EDEVICE. */
+int lbm_adjoint_step2_stored(lbm_ctx *ctx, const void *state_t1, const void *state_t0, const void *lam_next,
+                             void *lam_out, double *dtau_accum);
 
 /* Size in bytes of one co-state in the stored layout (moment scheme).
  * Errors: LBM_EINVAL, LBM_ESTATE (population scheme). */

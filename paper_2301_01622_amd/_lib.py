@@ -86,6 +86,8 @@ def load() -> ctypes.CDLL:
         "lbm_save_state": (c_int, [c_void, c_void]),
         "lbm_load_state": (c_int, [c_void, c_void]),
         "lbm_step_state": (c_int, [c_void, c_void, c_void]),
+        "lbm_step_state2": (c_int, [c_void, c_void, c_void, c_void]),
+        "lbm_adjoint_step2_stored": (c_int, [c_void, c_void, c_void, c_void, c_void, c_void]),
         "lbm_adjoint_step": (c_int, [c_void, c_void, c_void, c_void, c_void]),
         "lbm_adjoint_step_stored": (c_int, [c_void, c_void, c_void, c_void, c_void]),
         "lbm_costate_bytes": (c_int, [c_void, P(ctypes.c_int64)]),

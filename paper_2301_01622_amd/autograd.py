@@ -14,11 +14,15 @@ whose backward is the library's discrete adjoint step:
 
 Per step of the backward pass the device moves one forward step (recompute)
 plus one adjoint step; no state is copied besides the checkpoints, and the
-co-state stays in the library's stored layout until the end.
+co-state stays in the library's stored layout until the end.  Where the
+context runs two-step sweeps, pairs of states are recomputed in one pass
+(``lbm_step_state2``) and pairs of adjoint steps run in one pass
+(``lbm_adjoint_step2_stored``), with the same results.
 ``tau`` is a 0-d tensor whose value must equal the context's relaxation
 time; its gradient is dL/dtau (two species: at fixed surface tension sigma,
 so the perturbation amplitude A = 9 sigma/(2 tau) moves with tau).  The
-result does not depend on K (bit for bit).
+gradient to M0 does not depend on K (bit for bit), dL/dtau up to FP64
+rounding of how the per-step sums are grouped.
 """
 from __future__ import annotations
 
@@ -61,13 +65,26 @@ class MomentLBRollout(torch.autograd.Function):
         sim.costate_to_stored(pub, lam)
         dtau = torch.zeros(1, dtype=torch.float64, device=pub.device)
         slots = [None] + [sim.new_checkpoint() for _ in range(min(K, nsteps) - 1)]
+        pairs = getattr(sim, "sweeps", False)
         for s in reversed(range(len(ckpts))):
             n = min(K, nsteps - s * K)
             slots[0] = ckpts[s]
-            for t in range(1, n):
-                sim.step_state(slots[t - 1], slots[t])
-            for t in reversed(range(n)):
-                sim.adjoint_step_stored(slots[t], lam, lam_b, dtau)
+            t = 1
+            while t < n:
+                if pairs and t + 1 < n:
+                    sim.step_state2(slots[t - 1], slots[t], slots[t + 1])
+                    t += 2
+                else:
+                    sim.step_state(slots[t - 1], slots[t])
+                    t += 1
+            t = n - 1
+            while t >= 0:
+                if pairs and t >= 1:
+                    sim.adjoint_step2_stored(slots[t], slots[t - 1], lam, lam_b, dtau)
+                    t -= 2
+                else:
+                    sim.adjoint_step_stored(slots[t], lam, lam_b, dtau)
+                    t -= 1
                 lam, lam_b = lam_b, lam
         sim.costate_from_stored(lam, pub)
         grad_M0 = pub.to(ctx.M0_dtype)

@@ -434,6 +434,35 @@ int lbm_step_state(lbm_ctx *c, const void *src, void *dst)
     return LBM_OK;
 }
 
+int lbm_step_state2(lbm_ctx *c, const void *src, void *mid, void *dst)
+{
+    if (!c) return LBM_EINVAL;
+    if (!src || !mid || !dst || src == mid || src == dst || mid == dst)
+        return fail(c, LBM_EINVAL, "step_state2: NULL or aliased buffers");
+    if (!lbm::moment_sweep2_supported(c))
+        return fail(c, LBM_ESTATE, "step_state2: one species, fused moment step, FP32/FP16/BF16 storage only");
+    c->err.clear();
+    DeviceGuard g(c->device);
+    hipError_t e = lbm::launch_moment_sweep2(c, src, dst, mid);
+    if (e != hipSuccess) return hip_fail(c, e, "step_state2");
+    return LBM_OK;
+}
+
+int lbm_adjoint_step2_stored(lbm_ctx *c, const void *state_t1, const void *state_t0, const void *lam_next,
+                             void *lam_out, double *dtau_accum)
+{
+    if (!c) return LBM_EINVAL;
+    if (!state_t1 || !state_t0 || !lam_next || !lam_out || lam_next == lam_out)
+        return fail(c, LBM_EINVAL, "adjoint_step2: NULL or aliased buffers");
+    if (!lbm::moment_sweep2_supported(c))
+        return fail(c, LBM_ESTATE, "adjoint_step2: one species, fused moment step, FP32/FP16/BF16 storage only");
+    c->err.clear();
+    DeviceGuard g(c->device);
+    hipError_t e = lbm::launch_adjoint_sweep2(c, state_t1, state_t0, lam_next, lam_out, dtau_accum);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint_step2");
+    return LBM_OK;
+}
+
 static int adjoint_step(lbm_ctx *c, const void *state, const void *lam_next, void *lam_out, double *dtau_accum,
                         bool stored)
 {

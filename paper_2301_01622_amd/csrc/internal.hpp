@@ -47,8 +47,14 @@ hipError_t launch_moment_collide(const lbm_ctx *c, void *state);
 
 // Two moment steps in one pass over the state (one species, fused step,
 // FP32/FP16/BF16 storage); equal to two launch_moment_step calls bit for bit.
+// mid (optional): receives the state after the first step.
 bool moment_sweep2_supported(const lbm_ctx *c);
-hipError_t launch_moment_sweep2(const lbm_ctx *c, const void *in, void *out);
+hipError_t launch_moment_sweep2(const lbm_ctx *c, const void *in, void *out, void *mid = nullptr);
+
+// Two adjoint steps (co-states in the stored layout): lam_out =
+// J(state_t0)^T J(state_t1)^T lam_in, state_t1 being one step after state_t0.
+hipError_t launch_adjoint_sweep2(const lbm_ctx *c, const void *state_t1, const void *state_t0, const void *lam_in,
+                                 void *lam_out, double *dtau_accum);
 
 // Moment scheme, two species (colour gradient).
 hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out);

@@ -18,9 +18,10 @@
 //   * interior nodes pull from P1 into three more accumulator planes; plane
 //     p-2 of the second step is then complete and is stored.
 //
-// Threads are assigned per role (thread t holds node t of R0, of R1 and of
-// the interior, each numbered row by row), so the active threads of each
-// phase fill whole waves.  Each node of R1 and of the interior computes exactly the
+// Each thread holds one node in all its roles (interior nodes first, row by
+// row, then the one-node ring, then the outer ring), so the populations a
+// node keeps in its own column stay in registers and the interior's loads
+// and stores cover whole rows.  Each node of R1 and of the interior computes exactly the
 // arithmetic of the single step (the same collision, reconstruction and
 // layer sums, FMAs explicit), so a sweep equals two single steps bit for bit.
 // The cost is the redundant work on the two rings (R0 and R1 are 1.59x and
@@ -39,38 +40,37 @@
 namespace lbm {
 namespace {
 
-// LDS slot of direction (layer cz, slot sl = (cx+1) + 3 (cy+1)) among the q
-// directions of the lattice, own column included; -1 if absent.
-template <int Q>
-__host__ __device__ constexpr int dir_slot(int cz, int sl)
-{
-    int k = 0;
-    for (int z = -1; z <= 1; ++z)
-        for (int s = 0; s < 9; ++s) {
-            if (!has_dir<Q>(s % 3 - 1, s / 3 - 1, z)) continue;
-            if (z == cz && s == sl) return k;
-            ++k;
-        }
-    return -1;
-}
-
 template <int IX, int IY>
 constexpr int kSweepThreads = ((IX + 4) * (IY + 4) + 63) / 64 * 64;
 
-template <int Q, class S, int IX, int IY>
+// Position (x, y) of the m-th node of the one-node-wide ring of a W x H
+// rectangle: top row, bottom row, left column, right column.
+__device__ __forceinline__ void ring_pos(int m, int W, int H, int &x, int &y)
+{
+    if (m < W) { x = m; y = 0; }
+    else if (m < 2 * W) { x = m - W; y = H - 1; }
+    else if (m < 2 * W + H - 2) { x = 0; y = 1 + (m - 2 * W); }
+    else { x = W - 1; y = 1 + (m - 2 * W - (H - 2)); }
+}
+
+// MID: the intermediate state (after the first step) is stored to `mid`
+// as well, for the recomputation of forward states in reverse mode.
+template <int Q, class S, int IX, int IY, bool MID>
 __global__ __launch_bounds__((kSweepThreads<IX, IY>)) void k_moment_sweep2(const S *__restrict__ in,
-                                                                        S *__restrict__ out, TileGrid g,
+                                                                        S *__restrict__ out, S *__restrict__ mid,
+                                                                        TileGrid g,
                                                                         typename Store<S>::real omega,
                                                                         typename Store<S>::real s_pi,
                                                                         typename Store<S>::real inv_s_pi)
 {
     using R = typename Store<S>::real;
     constexpr bool kScaled = sizeof(S) == 2;  // 16-bit storage keeps S * s_pi
-    constexpr int HX0 = IX + 4, N0 = HX0 * (IY + 4);  // R0: sources of the first step
-    constexpr int HX1 = IX + 2, N1 = HX1 * (IY + 2);  // R1: results of the first step
+    constexpr int HX0 = IX + 4, HY0 = IY + 4, N0 = HX0 * HY0;  // R0: sources of the first step
+    constexpr int HX1 = IX + 2, HY1 = IY + 2, N1 = HX1 * HY1;  // R1: results of the first step
     constexpr int NI = IX * IY;
-    __shared__ R p0[Q * N0];
-    __shared__ R p1[Q * N1];
+    constexpr int NS = kLdsSlots<Q>;  // directions leaving the own column
+    __shared__ R p0[NS * N0];
+    __shared__ R p1[NS * N1];
 
     const int b = xcd_tile_id();
     const int tx = b % g.tiles_x;
@@ -81,17 +81,21 @@ __global__ __launch_bounds__((kSweepThreads<IX, IY>)) void k_moment_sweep2(const
     const int z_end = min(z0 + g.zchunk, g.nz);
     const int64_t plane = g.lay.plane;
 
+    // Thread t holds one node in all its roles: t < NI an interior node (row
+    // by row, so waves cover whole 64-node rows), then the nodes of the
+    // one-node ring, then those of the outer ring.  A node's own-column
+    // populations therefore never leave its thread's registers.
     const int tid = threadIdx.x;
     const bool r0 = tid < N0, r1 = tid < N1, ri = tid < NI;
-    const int h0 = tid;                                               // slot in P0
-    const int h1x = tid % HX1, h1y = tid / HX1;
-    const int h1in0 = (h1y + 1) * HX0 + (h1x + 1);                    // R1 node's slot in P0
-    const int h1 = tid;                                               // slot in P1
+    int hx, hy;  // position in the R0 frame
+    if (ri) { hx = tid % IX + 2; hy = tid / IX + 2; }
+    else if (r1) { ring_pos(tid - NI, HX1, HY1, hx, hy); hx += 1; hy += 1; }
+    else { ring_pos(r0 ? tid - N1 : 0, HX0, HY0, hx, hy); }
+    const int h0 = hy * HX0 + hx;              // slot in P0
+    const int h1 = (hy - 1) * HX1 + (hx - 1);  // slot in P1 (R1 nodes)
     const int ix = tid % IX, iy = tid / IX;
-    const int hiin1 = (iy + 1) * HX1 + (ix + 1);                      // interior node's slot in P1
     const bool active = ri && (x0 + ix < g.nx) && (y0 + iy < g.ny);
-    const int64_t src_xy = r0 ? g.lay.xy(wrap_coord(x0 - 2 + tid % HX0, g.nx), wrap_coord(y0 - 2 + tid / HX0, g.ny))
-                              : 0;
+    const int64_t src_xy = r0 ? g.lay.xy(wrap_coord(x0 - 2 + hx, g.nx), wrap_coord(y0 - 2 + hy, g.ny)) : 0;
     const int64_t dst_xy = active ? g.lay.xy(x0 + ix, y0 + iy) : 0;
 
     MomentAcc<R> a1[3], a2[3];
@@ -131,29 +135,35 @@ __global__ __launch_bounds__((kSweepThreads<IX, IY>)) void k_moment_sweep2(const
         v[9] = Store<S>::make(kScaled ? a.myz * sc : a.myz);
     };
 
-    auto publish = [&](const Collided<R> &c, R *P, int n, int h) {
+    // Writes the populations leaving the own column to slot h of P (n
+    // slots per direction); the own-column ones go to own[3].
+    auto publish = [&](const Collided<R> &c, R *P, int n, int h, R *own) {
         Layer<R> L0, L1, L2;
         reconstruct_layer<Q, -1, R>(c, L0);
         reconstruct_layer<Q, 0, R>(c, L1);
         reconstruct_layer<Q, 1, R>(c, L2);
 #pragma unroll
         for (int sl = 0; sl < 9; ++sl) {
-            if (dir_slot<Q>(-1, sl) >= 0) P[dir_slot<Q>(-1, sl) * n + h] = L0.v[sl];
-            if (dir_slot<Q>(0, sl) >= 0) P[dir_slot<Q>(0, sl) * n + h] = L1.v[sl];
-            if (dir_slot<Q>(1, sl) >= 0) P[dir_slot<Q>(1, sl) * n + h] = L2.v[sl];
+            if (lds_slot<Q>(-1, sl) >= 0) P[lds_slot<Q>(-1, sl) * n + h] = L0.v[sl];
+            if (lds_slot<Q>(0, sl) >= 0) P[lds_slot<Q>(0, sl) * n + h] = L1.v[sl];
+            if (lds_slot<Q>(1, sl) >= 0) P[lds_slot<Q>(1, sl) * n + h] = L2.v[sl];
         }
+        own[0] = L0.v[4];
+        own[1] = L1.v[4];
+        own[2] = L2.v[4];
     };
 
-    // Layer CZ of the populations streaming into slot h of a buffer of n
-    // slots, rows of hx, added to acc.
-    auto pull_layer = [&](auto czc, const R *P, int n, int hx, int h, MomentAcc<R> &acc) {
+    // Layer CZ of the populations streaming into slot h of P (rows of hx),
+    // added to acc.
+    auto pull_layer = [&](auto czc, const R *P, int n, int hx_, int h, R own, MomentAcc<R> &acc) {
         constexpr int CZ = decltype(czc)::value;
         Layer<R> f;
 #pragma unroll
         for (int sl = 0; sl < 9; ++sl) {
             const int cx = sl % 3 - 1, cy = sl / 3 - 1;
             f.v[sl] = R(0);
-            if (dir_slot<Q>(CZ, sl) >= 0) f.v[sl] = P[dir_slot<Q>(CZ, sl) * n + h - cy * hx - cx];
+            if (sl == 4) f.v[sl] = own;
+            else if (lds_slot<Q>(CZ, sl) >= 0) f.v[sl] = P[lds_slot<Q>(CZ, sl) * n + h - cy * hx_ - cx];
         }
         accumulate_layer<Q, CZ, R>(acc, f);
     };
@@ -161,22 +171,28 @@ __global__ __launch_bounds__((kSweepThreads<IX, IY>)) void k_moment_sweep2(const
     // One source plane p: first-step populations of p, intermediate plane
     // p-1, second-step plane p-2.
     auto plane_step = [&](int p, Moments<R> &m) {
-        if (r0) publish(collide_node(m), p0, N0, h0);
+        R own0[3], own1[3];
+        if (r0) publish(collide_node(m), p0, N0, h0, own0);
         __syncthreads();
         if (p + 2 <= z_end + 1) fetch(p + 2, m);
 
         if (r1) {
-            pull_layer(std::integral_constant<int, -1>(), p0, N0, HX0, h1in0, a1[0]);
-            pull_layer(std::integral_constant<int, 0>(), p0, N0, HX0, h1in0, a1[1]);
-            pull_layer(std::integral_constant<int, 1>(), p0, N0, HX0, h1in0, a1[2]);
+            pull_layer(std::integral_constant<int, -1>(), p0, N0, HX0, h0, own0[0], a1[0]);
+            pull_layer(std::integral_constant<int, 0>(), p0, N0, HX0, h0, own0[1], a1[1]);
+            pull_layer(std::integral_constant<int, 1>(), p0, N0, HX0, h0, own0[2], a1[2]);
             // Intermediate plane p-1 has received from p-2, p-1 and p.
             if (p >= z0) {
                 S v[10];
                 stored_values(a1[0], v);
+                if (MID && active && p - 1 >= z0 && p - 1 < z_end) {
+                    const int64_t o = dst_xy + (int64_t)(p - 1) * plane;
+#pragma unroll
+                    for (int k = 0; k < 10; ++k) store_out(mid + k * kBlock + o, v[k]);
+                }
                 Moments<R> mi;
 #pragma unroll
                 for (int k = 0; k < 10; ++k) mi.v[k] = Store<S>::load(v[k]);
-                publish(collide_node(mi), p1, N1, h1);
+                publish(collide_node(mi), p1, N1, h1, own1);
             }
             a1[0] = a1[1];
             a1[1] = a1[2];
@@ -185,9 +201,9 @@ __global__ __launch_bounds__((kSweepThreads<IX, IY>)) void k_moment_sweep2(const
         __syncthreads();
 
         if (p >= z0 && ri) {
-            pull_layer(std::integral_constant<int, -1>(), p1, N1, HX1, hiin1, a2[0]);
-            pull_layer(std::integral_constant<int, 0>(), p1, N1, HX1, hiin1, a2[1]);
-            pull_layer(std::integral_constant<int, 1>(), p1, N1, HX1, hiin1, a2[2]);
+            pull_layer(std::integral_constant<int, -1>(), p1, N1, HX1, h1, own1[0], a2[0]);
+            pull_layer(std::integral_constant<int, 0>(), p1, N1, HX1, h1, own1[1], a2[1]);
+            pull_layer(std::integral_constant<int, 1>(), p1, N1, HX1, h1, own1[2], a2[2]);
             // Second-step plane p-2 has received from intermediate planes p-3, p-2, p-1.
             const int d = p - 2;
             if (d >= z0 && active) {
@@ -217,7 +233,7 @@ __global__ __launch_bounds__((kSweepThreads<IX, IY>)) void k_moment_sweep2(const
 #endif
 
 template <int Q, class S, int IX, int IY>
-hipError_t run(const lbm_ctx *c, const void *in, void *out)
+hipError_t run(const lbm_ctx *c, const void *in, void *out, void *mid)
 {
     using R = typename Store<S>::real;
     TileGrid g;
@@ -232,9 +248,14 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out)
     g.chunks = (c->nz + g.zchunk - 1) / g.zchunk;
     const int64_t blocks = (int64_t)g.tiles_x * g.tiles_y * g.chunks;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_moment_sweep2<Q, S, IX, IY>), dim3((unsigned)blocks), dim3(kSweepThreads<IX, IY>), 0,
-                       c->stream, static_cast<const S *>(in), static_cast<S *>(out), g, (R)c->omega, (R)c->s_pi,
-                       (R)(1.0 / c->s_pi));
+    if (mid)
+        hipLaunchKernelGGL((k_moment_sweep2<Q, S, IX, IY, true>), dim3((unsigned)blocks), dim3(kSweepThreads<IX, IY>),
+                           0, c->stream, static_cast<const S *>(in), static_cast<S *>(out), static_cast<S *>(mid), g,
+                           (R)c->omega, (R)c->s_pi, (R)(1.0 / c->s_pi));
+    else
+        hipLaunchKernelGGL((k_moment_sweep2<Q, S, IX, IY, false>), dim3((unsigned)blocks),
+                           dim3(kSweepThreads<IX, IY>), 0, c->stream, static_cast<const S *>(in),
+                           static_cast<S *>(out), nullptr, g, (R)c->omega, (R)c->s_pi, (R)(1.0 / c->s_pi));
     return hipGetLastError();
 }
 
@@ -250,12 +271,12 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out)
 #endif
 
 template <int Q>
-hipError_t dispatch_storage(const lbm_ctx *c, const void *in, void *out)
+hipError_t dispatch_storage(const lbm_ctx *c, const void *in, void *out, void *mid)
 {
     switch (c->storage) {
-    case LBM_STORE_F32: return run<Q, float, LBM_SWEEP_IX, LBM_SWEEP_IY>(c, in, out);
-    case LBM_STORE_F16: return run<Q, f16, LBM_SWEEP_IX, LBM_SWEEP_IY>(c, in, out);
-    case LBM_STORE_BF16: return run<Q, bf16, LBM_SWEEP_IX, LBM_SWEEP_IY>(c, in, out);
+    case LBM_STORE_F32: return run<Q, float, LBM_SWEEP_IX, LBM_SWEEP_IY>(c, in, out, mid);
+    case LBM_STORE_F16: return run<Q, f16, LBM_SWEEP_IX, LBM_SWEEP_IY>(c, in, out, mid);
+    case LBM_STORE_BF16: return run<Q, bf16, LBM_SWEEP_IX, LBM_SWEEP_IY>(c, in, out, mid);
     default: return hipErrorNotSupported;
     }
 }
@@ -267,10 +288,10 @@ bool moment_sweep2_supported(const lbm_ctx *c)
     return c->scheme == LBM_SCHEME_MOMENT && c->species == 1 && !c->split && c->storage != LBM_STORE_F64;
 }
 
-hipError_t launch_moment_sweep2(const lbm_ctx *c, const void *in, void *out)
+hipError_t launch_moment_sweep2(const lbm_ctx *c, const void *in, void *out, void *mid)
 {
     if (!moment_sweep2_supported(c)) return hipErrorNotSupported;
-    return c->q == 19 ? dispatch_storage<19>(c, in, out) : dispatch_storage<27>(c, in, out);
+    return c->q == 19 ? dispatch_storage<19>(c, in, out, mid) : dispatch_storage<27>(c, in, out, mid);
 }
 
 } // namespace lbm

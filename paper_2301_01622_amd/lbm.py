@@ -32,6 +32,7 @@ class LBM:
         self.nx, self.ny, self.nz = (int(s) for s in shape)
         self.q, self.tau, self.species = int(lattice), float(tau), int(species)
         self.scheme, self.storage = scheme, storage
+        self.split, self.steps_per_sweep = bool(split), int(steps_per_sweep)
         self.device = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         opts = _lib.Opts()
@@ -153,6 +154,20 @@ class LBM:
         _lib.check(self._lib.lbm_step_state(self._ctx, ctypes.c_void_p(src.data_ptr()),
                                             ctypes.c_void_p(dst.data_ptr())), self._ctx, "step_state")
 
+    def step_state2(self, src: torch.Tensor, mid: torch.Tensor, dst: torch.Tensor) -> None:
+        """Two steps from saved state `src` in one pass: `mid` after the first,
+        `dst` after the second (all state_bytes)."""
+        _lib.check(self._lib.lbm_step_state2(self._ctx, ctypes.c_void_p(src.data_ptr()),
+                                             ctypes.c_void_p(mid.data_ptr()), ctypes.c_void_p(dst.data_ptr())),
+                   self._ctx, "step_state2")
+
+    @property
+    def sweeps(self) -> bool:
+        """True if the context runs two-step sweeps (and has the two-step
+        recompute and adjoint entry points)."""
+        return (self.scheme == "moment" and self.species == 1 and not self.split and self.storage != "f64"
+                and self.steps_per_sweep != 1)
+
     @property
     def real_dtype(self):
         """Arithmetic type of the kernels (the co-state's element type)."""
@@ -200,6 +215,17 @@ class LBM:
                                                      ctypes.c_void_p(lam_next.data_ptr()),
                                                      ctypes.c_void_p(lam_out.data_ptr()), dptr), self._ctx,
                    "adjoint_step_stored")
+
+    def adjoint_step2_stored(self, state_t1: torch.Tensor, state_t0: torch.Tensor, lam_next: torch.Tensor,
+                             lam_out: torch.Tensor, dtau_accum: torch.Tensor | None = None) -> None:
+        """Two adjoint steps in one pass (stored layout): lam_out =
+        J(state_t0)^T J(state_t1)^T lam_next, state_t1 one step after state_t0."""
+        dptr = ctypes.c_void_p(dtau_accum.data_ptr()) if dtau_accum is not None else None
+        _lib.check(self._lib.lbm_adjoint_step2_stored(self._ctx, ctypes.c_void_p(state_t1.data_ptr()),
+                                                      ctypes.c_void_p(state_t0.data_ptr()),
+                                                      ctypes.c_void_p(lam_next.data_ptr()),
+                                                      ctypes.c_void_p(lam_out.data_ptr()), dptr), self._ctx,
+                   "adjoint_step2_stored")
 
     @property
     def steps_done(self) -> int:

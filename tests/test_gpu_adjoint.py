@@ -98,7 +98,8 @@ def test_rollout_independent_of_checkpoint_interval(mods):
         sim.close()
     for g, gt in grads[1:]:
         np.testing.assert_array_equal(g, grads[0][0])
-        assert gt == grads[0][1]
+        # Two-step adjoint passes group the per-step FP64 sums differently.
+        assert abs(gt - grads[0][1]) <= 1e-12 * abs(grads[0][1])
 
 
 def test_rollout_gradient_finite_differences(mods):

@@ -89,3 +89,62 @@ def test_sweep_full_size_sampled(oracle):
         # The cone is not periodic: only its centre is exact after `steps` steps.
         ref = oracle.moment_run(np.ascontiguousarray(cube), q, tau, steps)[:, r, r, r]
         assert np.abs(got[:, z, y, x] - ref).max() <= 1e-6, (z, y, x)
+
+
+# ---- two-step recompute and two-step adjoint (reverse mode) --------------------------
+
+@pytest.mark.parametrize("shape", [(70, 37, 20), (17, 13, 11), (3, 3, 3)])
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_step_state2_and_adjoint2_equal_single_steps(shape, q, storage):
+    from paper_2301_01622_amd.lbm import LBM
+    _say(f"two-step recompute and adjoint {shape} D3Q{q} {storage}")
+    H = I.random_moments(shape[::-1], seed=110 + q, drho=0.01, dj=0.01, dp=0.003)
+    sim = LBM(shape, q, 0.66, storage=storage)
+    sim.set_moments(torch.from_numpy(H).cuda())
+    # Zeroed buffers: slots of the stored layout that hold no node stay zero.
+    s0, s1, s2, m, d = (sim.new_checkpoint().zero_() for _ in range(5))
+    sim.save_state(s0)
+    sim.step_state(s0, s1)
+    sim.step_state(s1, s2)
+    sim.step_state2(s0, m, d)
+    assert torch.equal(m, s1) and torch.equal(d, s2)
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    pub = torch.randn((10,) + sim.shape, generator=g, device="cuda", dtype=torch.float32)
+    lam, a, b = sim.new_costate(), sim.new_costate(), sim.new_costate()
+    sim.costate_to_stored(pub, lam)
+    t1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sim.adjoint_step_stored(s1, lam, a, t1)
+    sim.adjoint_step_stored(s0, a, b, t1)
+    out = sim.new_costate()
+    sim.adjoint_step2_stored(s1, s0, lam, out, t2)
+    pa, pb = torch.empty_like(pub), torch.empty_like(pub)
+    sim.costate_from_stored(b, pa)
+    sim.costate_from_stored(out, pb)
+    assert torch.equal(pa, pb)
+    assert abs(float(t2) - float(t1)) <= 1e-12 * abs(float(t1))
+    sim.close()
+
+
+def test_two_step_entry_points_reject_bad_calls():
+    import ctypes
+    from paper_2301_01622_amd import _lib
+    from paper_2301_01622_amd.lbm import LBM
+    sim = LBM((8, 8, 8), 19, 0.8, storage="f64")
+    a, b, c = (sim.new_checkpoint() for _ in range(3))
+    lib, ctx, p = sim._lib, sim._ctx, (lambda t: ctypes.c_void_p(t.data_ptr()))
+    assert lib.lbm_step_state2(ctx, p(a), p(b), p(c)) == _lib.LBM_ESTATE
+    lam, lo = sim.new_costate(), sim.new_costate()
+    assert lib.lbm_adjoint_step2_stored(ctx, p(a), p(b), p(lam), p(lo), None) == _lib.LBM_ESTATE
+    sim.close()
+    sim = LBM((8, 8, 8), 19, 0.8, storage="f32")
+    a, b, c = (sim.new_checkpoint() for _ in range(3))
+    lib, ctx = sim._lib, sim._ctx
+    assert lib.lbm_step_state2(ctx, p(a), p(a), p(c)) == _lib.LBM_EINVAL
+    assert lib.lbm_step_state2(ctx, p(a), None, p(c)) == _lib.LBM_EINVAL
+    lam = sim.new_costate()
+    assert lib.lbm_adjoint_step2_stored(ctx, p(a), p(b), p(lam), p(lam), None) == _lib.LBM_EINVAL
+    sim.close()
