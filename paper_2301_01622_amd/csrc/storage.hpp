@@ -43,16 +43,11 @@ template <>
 struct Store<bf16> {
     using real = float;
     __device__ __forceinline__ static float load(bf16 v) { return __uint_as_float((uint32_t)v.bits << 16); }
+    // The hardware conversion of gfx950 (round to nearest even, NaN stays NaN).
     __device__ __forceinline__ static bf16 make(float v)
     {
-        uint32_t u = __float_as_uint(v);
         bf16 r;
-        if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu) != 0u) {
-            r.bits = (uint16_t)((u >> 16) | 0x0040u); // quiet NaN, sign kept
-        } else {
-            u += 0x7fffu + ((u >> 16) & 1u);
-            r.bits = (uint16_t)(u >> 16);
-        }
+        r.bits = __builtin_bit_cast(uint16_t, (__bf16)v);
         return r;
     }
 };

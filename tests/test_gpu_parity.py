@@ -307,3 +307,30 @@ def test_translation_bitwise_wide_tiles(LBM, storage):
     a = _gpu_run_from_moments(LBM, H, 27, 0.6, 6, storage=storage)
     b = _gpu_run_from_moments(LBM, Hs, 27, 0.6, 6, storage=storage)
     np.testing.assert_array_equal(np.roll(a, shift, axis=(1, 2, 3)), b)
+
+
+def test_bf16_storage_rounds_to_nearest_even(LBM):
+    """The stored BF16 value of a momentum component is its FP32 value rounded
+    to nearest even (ties, just-below and just-above ties, negative values),
+    checked bit for bit against a rounding written out on the host."""
+    rng = np.random.default_rng(12)
+    n = 8 * 8 * 8
+    hi = rng.integers(0x3a00, 0x3e00, n).astype(np.uint32)       # |j| in about [5e-4, 0.1)
+    lo = rng.choice(np.array([0x8000, 0x7fff, 0x8001, 0x0000, 0xffff, 0x4321], dtype=np.uint32), n)
+    bits = (hi << 16) | lo
+    bits[::2] |= np.uint32(0x80000000)
+    j32 = bits.view(np.float32)
+    # round to nearest even on the 16 dropped bits
+    keep = bits >> 16
+    rem = bits & 0xffff
+    up = (rem > 0x8000) | ((rem == 0x8000) & ((keep & 1) == 1))
+    ref = ((keep + up.astype(np.uint32)) << 16).view(np.float32).astype(np.float64)
+    H = np.zeros((10, 8, 8, 8))
+    H[0] = 1.0
+    H[1] = j32.astype(np.float64).reshape(8, 8, 8)
+    H[4:7] = 1.0 / 3.0
+    sim = LBM((8, 8, 8), 19, 0.8, storage="bf16")
+    sim.set_moments(torch.from_numpy(H).cuda())
+    got = sim.get_moments(torch.float64).cpu().numpy()[1].ravel()
+    sim.close()
+    np.testing.assert_array_equal(got, ref)
