@@ -45,8 +45,10 @@ def _load():
             "ora_populations_from_moments": (i, [i, l, dp, dp]),
             "ora_moments_from_populations": (i, [i, l, dp, dp]),
             "ora_population_run": (i, [i, i, i, i, d, i, i, dp]),
-            "ora_cg_moment_run": (i, [i, i, i, i, d, d, d, i, dp]),
-            "ora_cg_population_run": (i, [i, i, i, i, d, d, d, i, i, dp, dp]),
+            "ora_cg_moment_run": (i, [i, i, i, i, d, d, d, d, i, i, dp]),
+            "ora_cg_population_run": (i, [i, i, i, i, d, d, d, i, d, i, i, dp, dp]),
+            "ora_nc_force": (i, [i, i, i, i, dp, d, i, dp, ip]),
+            "ora_forced_collide_node": (i, [i, d, d, dp, dp, dp, dp]),
             "ora_moment_adjoint_step": (i, [i, i, i, i, d, dp, dp, dp, dp]),
             "ora_cg_adjoint_step": (i, [i, i, i, i, d, d, d, dp, dp, dp, dp]),
         }
@@ -168,24 +170,49 @@ def population_run(f, q: int, tau: float, nsteps: int, regularize: bool = False)
     return f
 
 
-def cg_moment_run(H, q: int, tau: float, A: float, beta: float, nsteps: int) -> np.ndarray:
-    """Two-component colour-gradient scheme without populations."""
+def cg_moment_run(H, q: int, tau: float, A: float, beta: float, nsteps: int, Ah: float = 0.0,
+                  hmax: int = 0) -> np.ndarray:
+    """Two-component colour-gradient scheme without populations (with the
+    near-contact force of strength Ah and probe range hmax if Ah != 0)."""
     H = np.array(H, dtype=np.float64, order="C", copy=True)
     _, nz, ny, nx = H.shape
     assert H.shape[0] == 11
-    _check(_load().ora_cg_moment_run(q, nx, ny, nz, tau, A, beta, nsteps, _dp(H)), "cg_moment_run")
+    _check(_load().ora_cg_moment_run(q, nx, ny, nz, tau, A, beta, Ah, hmax, nsteps, _dp(H)), "cg_moment_run")
     return H
 
 
 def cg_population_run(f1, f2, q: int, tau: float, A: float, beta: float, nsteps: int,
-                      regularize: bool = False):
+                      regularize: bool = False, Ah: float = 0.0, hmax: int = 0):
     """Two-component colour-gradient scheme with populations (one set per species)."""
     f1 = np.array(f1, dtype=np.float64, order="C", copy=True)
     f2 = np.array(f2, dtype=np.float64, order="C", copy=True)
     _, nz, ny, nx = f1.shape
-    _check(_load().ora_cg_population_run(q, nx, ny, nz, tau, A, beta, int(regularize), nsteps,
+    _check(_load().ora_cg_population_run(q, nx, ny, nz, tau, A, beta, int(regularize), Ah, hmax, nsteps,
                                          _dp(f1), _dp(f2)), "cg_population_run")
     return f1, f2
+
+
+def forced_collide_node(q: int, tau: float, rho: float, j, P, F) -> np.ndarray:
+    """Post-collision populations of one node under body force F (BGK with
+    Guo's forcing; no colour-gradient operators)."""
+    j = np.ascontiguousarray(j, dtype=np.float64)
+    P = np.ascontiguousarray(P, dtype=np.float64).reshape(9)
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    out = np.zeros(q)
+    _check(_load().ora_forced_collide_node(q, tau, rho, _dp(j), _dp(P), _dp(F), _dp(out)), "forced_collide_node")
+    return out
+
+
+def nc_force(phi, q: int, Ah: float, hmax: int):
+    """Near-contact force field F (3, nz, ny, nx) and film distance h (nz, ny,
+    nx; 0 where none) from a phase field phi (nz, ny, nx)."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    nz, ny, nx = phi.shape
+    F = np.zeros((3,) + phi.shape)
+    h = np.zeros(phi.shape, dtype=np.int32)
+    _check(_load().ora_nc_force(q, nx, ny, nz, _dp(phi), Ah, hmax, _dp(F),
+                                h.ctypes.data_as(ctypes.POINTER(ctypes.c_int))), "nc_force")
+    return F, h
 
 
 def cg_populations_from_moments(H11, q: int):
