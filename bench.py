@@ -182,6 +182,17 @@ def two_component(steps: int, warmup: int):
         pms = time_steps(ps, stream, steps, warmup)
         p_state, p_step = ps.memory_info()
         ps.close()
+        # The same collision with the near-contact force (A_h = 0.01, 4 probes):
+        # one extra pass per step computes the force field.
+        nc = {}
+        for scheme in ("moment", "population"):
+            ns = LBM((512, 256, 256), 19, 0.8, species=2, storage="f32", sigma=0.01, beta=0.7, scheme=scheme,
+                     stream=stream, nc_A=0.01, nc_hmax=4)
+            ns.set_equilibrium(torch.from_numpy(np.stack([r1, r2])).cuda(), torch.from_numpy(u).cuda())
+            t = time_steps(ns, stream, steps, warmup)
+            ns.close()
+            nc[scheme] = {"value": round(N / (t * 1e-3) / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(t, 5)}
+        nc["speedup_vs_population_lb"] = round(nc["population"]["ms_per_step"] / nc["moment"]["ms_per_step"], 3)
     return {
         "workload": "512x256x256 two-component droplet collision, D3Q19, FP32 (rho-1, rho1, j, P), tau=0.8, "
                     "sigma=0.01, beta=0.7, R=40, u=+-0.05",
@@ -200,6 +211,7 @@ def two_component(steps: int, warmup: int):
             "bytes_per_node_state": p_state // N,
         },
         "speedup_vs_population_lb": round(pms / ms, 3),
+        "near_contact": {"A_h": 0.01, "h_max": 4, **nc},
         "adjoint": adjoint,
     }
 

@@ -105,6 +105,16 @@ typedef struct {
                         storage (else LBM_EINVAL).  0 (default): 2 where available, else 1.
                         lbm_step falls back to single steps for an odd remainder and where
                         a check_every health check falls between the two steps */
+    double nc_A;     /* near-contact force of the LBNCI extension (Sec. III.C), two species:
+                        F = -A_h n delta_I, read as F = (nc_A/2) G at nodes from which a film
+                        of species 2 is crossed into another drop within nc_hmax nodes along
+                        the lattice direction closest to the outward normal, 0 elsewhere
+                        (G the colour gradient); added to the mixture collision with Guo's
+                        forcing.  0 (default) = off.  Non-zero needs two species and
+                        1 <= nc_hmax <= 32 (else LBM_EINVAL); the context then holds a
+                        scratch of 3 N reals (moment scheme 4 N) and the adjoint entry
+                        points give LBM_ESTATE */
+    int nc_hmax;     /* probe range of the near-contact force, nodes */
 } lbm_opts;
 
 /* Caller-owned moment buffers, see the layout above. */

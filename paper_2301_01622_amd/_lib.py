@@ -40,6 +40,8 @@ class Opts(ctypes.Structure):
         ("check_every", ctypes.c_int),
         ("split", ctypes.c_int),
         ("steps_per_sweep", ctypes.c_int),
+        ("nc_A", ctypes.c_double),
+        ("nc_hmax", ctypes.c_int),
     ]
 
 

@@ -103,6 +103,8 @@ void lbm_default_opts(lbm_opts *o)
     o->check_every = 0;
     o->split = 0;
     o->steps_per_sweep = 0;
+    o->nc_A = 0.0;
+    o->nc_hmax = 0;
 }
 
 const char *lbm_strerror(int code)
@@ -146,6 +148,9 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     if (!(o.s_pi >= 0.0) || !std::isfinite(o.s_pi)) return LBM_EINVAL;
     if (species == 2 && o.scheme == LBM_SCHEME_POPULATION && o.storage != LBM_STORE_F32) return LBM_EINVAL;
 
+    // Near-contact force: two species only, finite strength, 1..32 probes.
+    if (o.nc_A != 0.0 && (species != 2 || !std::isfinite(o.nc_A) || o.nc_hmax < 1 || o.nc_hmax > 32))
+        return LBM_EINVAL;
     // Two-step sweeps: one species, fused moment step, not FP64 storage.
     const bool sweep2_ok = o.scheme == LBM_SCHEME_MOMENT && species == 1 && o.split == 0 && o.storage != LBM_STORE_F64;
     if (o.steps_per_sweep < 0 || o.steps_per_sweep > 2 || (o.steps_per_sweep == 2 && !sweep2_ok)) return LBM_EINVAL;
@@ -170,6 +175,8 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     c->check_every = o.check_every;
     c->split = o.split;
     c->sweep = sweep;
+    c->nc_A = o.nc_A;
+    c->nc_hmax = o.nc_A != 0.0 ? o.nc_hmax : 0;
     c->elem = storage_bytes(o.storage);
     c->nfields = o.scheme == LBM_SCHEME_MOMENT ? (species == 1 ? 10 : 11) : lattice * species;
     c->lay = lbm::moment_layout(c->nx, c->ny, c->nfields);
@@ -194,6 +201,13 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     }
     if (c->scheme == LBM_SCHEME_POPULATION && species == 2 &&
         hipMalloc((void **)&c->scratch_phi, sizeof(float) * (size_t)c->N) != hipSuccess) {
+        lbm_destroy(c);
+        return LBM_ENOMEM;
+    }
+    // Near-contact force (3 N) and, for the moment scheme, its phase field (N).
+    if (c->nc_A != 0.0 &&
+        hipMalloc(&c->scratch_nc, c->elem * (size_t)c->N * (c->scheme == LBM_SCHEME_MOMENT ? 4 : 3)) != hipSuccess) {
+        c->scratch_nc = nullptr;
         lbm_destroy(c);
         return LBM_ENOMEM;
     }
@@ -228,6 +242,7 @@ int lbm_destroy(lbm_ctx *c)
     if (c->partials) (void)hipFree(c->partials);
     if (c->red_out) (void)hipFree(c->red_out);
     if (c->scratch_phi) (void)hipFree(c->scratch_phi);
+    if (c->scratch_nc) (void)hipFree(c->scratch_nc);
     if (c->scratch_adj) (void)hipFree(c->scratch_adj);
     delete c;
     return LBM_OK;
@@ -382,6 +397,7 @@ int lbm_memory_info(const lbm_ctx *c, int64_t *state_bytes, int64_t *step_bytes)
     const int64_t copies = c->scheme == LBM_SCHEME_POPULATION_AA ? 1 : 2;
     if (state_bytes)
         *state_bytes = copies * per_copy + (c->scratch_phi ? (int64_t)sizeof(float) * c->N : 0) +
+                       (c->scratch_nc ? (int64_t)c->elem * c->N * (c->scheme == LBM_SCHEME_MOMENT ? 4 : 3) : 0) +
                        (c->scratch_adj ? (int64_t)c->elem * c->lay3.plane * c->nz : 0);
     // Split approach: the collision pass reads all stored fields and writes S'
     // (6 fields), the streaming pass reads and writes all of them.
@@ -473,6 +489,7 @@ static int adjoint_step(lbm_ctx *c, const void *state, const void *lam_next, voi
         return fail(c, LBM_ESTATE, "adjoint_step: moment scheme only");
     if (c->species == 2 && c->storage != LBM_STORE_F32 && c->storage != LBM_STORE_F64)
         return fail(c, LBM_ESTATE, "adjoint_step: two species need FP32 or FP64 storage");
+    if (c->nc_A != 0.0) return fail(c, LBM_ESTATE, "adjoint_step: not with the near-contact force");
     c->err.clear();
     DeviceGuard g(c->device);
     if (c->species == 2 && !c->scratch_adj) {

@@ -77,9 +77,13 @@ __host__ __device__ constexpr double inv_speed(int cx, int cy, int cz)
                                                                                            : 0.57735026918962576451;
 }
 
-template <int Q, class R, int TX, int TY>
+// FORCE: a body force (three arrays of N values, x fastest) enters the
+// mixture collision with Guo's forcing: u* = (j + F/2)/rho in the
+// equilibrium, (1 - omega/2)(u* F + F u*) added to the collided S, j + F
+// streamed.
+template <int Q, class R, int TX, int TY, bool FORCE>
 __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R *__restrict__ out, TileGrid g,
-                                                    R omega, R A9, R beta)
+                                                    R omega, R A9, R beta, const R *__restrict__ frc)
 {
     constexpr int NT = TX * TY;
     constexpr int SX = TX + 2, SY = TY + 2, SN = SX * SY;  // source region (radius 1)
@@ -136,6 +140,13 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
     };
     const int64_t own_xy = xy_src(h0);
     const int64_t ring_xy = has_ring ? xy_src(hr) : 0;
+    // Offsets of the force arrays (public layout) of the two source nodes.
+    auto lin_src = [&](int h) -> int64_t {
+        return (int64_t)wrap_coord(x0 - 1 + h % SX, g.nx) + (int64_t)g.nx * wrap_coord(y0 - 1 + h / SX, g.ny);
+    };
+    const int64_t own_lin = FORCE ? lin_src(h0) : 0;
+    const int64_t ring_lin = FORCE && has_ring ? lin_src(hr) : 0;
+    const int64_t plane_lin = (int64_t)g.nx * g.ny;
     const int64_t outer_xy =
         has_outer ? g.lay.xy(wrap_coord(x0 - 2 + ko % FX, g.nx), wrap_coord(y0 - 2 + ko / FX, g.ny))
                   : 0;
@@ -145,6 +156,7 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
     struct PlaneRegs {
         M11 own, ring;
         R outer_dr, outer_r1;
+        R fox, foy, foz, frx, fry, frz;  // force at the two source nodes (FORCE)
     };
     PlaneRegs pa, pb;
     auto zwrap = [&](int p) { return p < 0 ? p + g.nz : (p >= g.nz ? p - g.nz : p); };
@@ -155,6 +167,17 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
         if (has_outer) {
             r.outer_dr = in[outer_xy + zo];
             r.outer_r1 = in[kBlock + outer_xy + zo];
+        }
+        if (FORCE) {
+            const int64_t zl = (int64_t)zwrap(p) * plane_lin;
+            r.fox = frc[own_lin + zl];
+            r.foy = frc[g.N + own_lin + zl];
+            r.foz = frc[2 * g.N + own_lin + zl];
+            if (has_ring) {
+                r.frx = frc[ring_lin + zl];
+                r.fry = frc[g.N + ring_lin + zl];
+                r.frz = frc[2 * g.N + ring_lin + zl];
+            }
         }
     };
     auto phi_of = [](R dr, R r1) { return fma_(R(2) * r1, reciprocal<R>(R(1) + dr), R(-1)); };
@@ -172,7 +195,7 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
     acc[2].zero();
 
     // Collides one source node (region slot h) and publishes h~ and f1.
-    auto publish = [&](int p, const M11 &v, int h, R *own_h, R *own_f) {
+    auto publish = [&](int p, const M11 &v, int h, R *own_h, R *own_f, R fx, R fy, R fz) {
         const int kc = src_to_phi(h);
         const R *phm = lds_phi + slot_of(p - 1) * FN;
         const R *ph0 = lds_phi + slot_of(p) * FN;
@@ -208,7 +231,25 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
         const R nx = Gx * invD, ny = Gy * invD, nz = Gz * invD;
 
         const R dr = v.v[0], r1 = v.v[1];
-        Collided<R> c = collide<R>(dr, v.v[2], v.v[3], v.v[4], v.v[5], v.v[6], v.v[7], v.v[8], v.v[9], v.v[10], omega);
+        Collided<R> c;
+        if (FORCE) {
+            // Guo's forcing: equilibrium at j* = j + F/2, source (1 - omega/2)(u* F + F u*).
+            const R jsx = fma_(R(0.5), fx, v.v[2]), jsy = fma_(R(0.5), fy, v.v[3]), jsz = fma_(R(0.5), fz, v.v[4]);
+            c = collide<R>(dr, jsx, jsy, jsz, v.v[5], v.v[6], v.v[7], v.v[8], v.v[9], v.v[10], omega);
+            const R k = (R(1) - R(0.5) * omega) * reciprocal<R>(R(1) + dr);
+            const R kx = k * jsx, ky = k * jsy, kz = k * jsz;
+            c.sxx = fma_(R(2) * kx, fx, c.sxx);
+            c.syy = fma_(R(2) * ky, fy, c.syy);
+            c.szz = fma_(R(2) * kz, fz, c.szz);
+            c.sxy = fma_(kx, fy, fma_(ky, fx, c.sxy));
+            c.sxz = fma_(kx, fz, fma_(kz, fx, c.sxz));
+            c.syz = fma_(ky, fz, fma_(kz, fy, c.syz));
+            c.jx = v.v[2] + fx;
+            c.jy = v.v[3] + fy;
+            c.jz = v.v[4] + fz;
+        } else {
+            c = collide<R>(dr, v.v[2], v.v[3], v.v[4], v.v[5], v.v[6], v.v[7], v.v[8], v.v[9], v.v[10], omega);
+        }
         // Perturbation: A/9 (G G - |G|^2 I)/D.
         const R a9 = A9 * invD;
         c.sxx = fma_(a9, fma_(Gx, Gx, -G2), c.sxx);
@@ -301,8 +342,8 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
         write_phi(p + 1, nxt);
         __syncthreads();
         R oh[3], of[3];
-        publish(p, cur.own, h0, oh, of);
-        if (has_ring) publish(p, cur.ring, hr, nullptr, nullptr);
+        publish(p, cur.own, h0, oh, of, cur.fox, cur.foy, cur.foz);
+        if (has_ring) publish(p, cur.ring, hr, nullptr, nullptr, cur.frx, cur.fry, cur.frz);
         __syncthreads();
         if (p + 2 <= z_end + 1) fetch(p + 2, cur);
         pull_layer(std::integral_constant<int, -1>(), oh[0], of[0]);
@@ -358,9 +399,18 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out)
     g.chunks = (c->nz + g.zchunk - 1) / g.zchunk;
     const int64_t blocks = (int64_t)g.tiles_x * g.tiles_y * g.chunks;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
-                       static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega, (R)(c->A / 9.0),
-                       (R)c->beta);
+    if (c->nc_A != 0.0) {
+        // Near-contact force of this state first (into the context's scratch).
+        hipError_t e = launch_nc_force(c, in, nullptr);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, true>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
+                           static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega, (R)(c->A / 9.0),
+                           (R)c->beta, static_cast<const R *>(c->scratch_nc));
+    } else {
+        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, false>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
+                           static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega, (R)(c->A / 9.0),
+                           (R)c->beta, nullptr);
+    }
     return hipGetLastError();
 }
 

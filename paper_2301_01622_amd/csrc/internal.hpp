@@ -19,6 +19,9 @@ struct lbm_ctx {
     int check_every = 0;
     int split = 0;    // moment scheme run as the split approach (collision pass + streaming pass)
     int sweep = 1;    // time steps per pass over the state (1, or 2: two-step sweeps)
+    double nc_A = 0.0;  // near-contact force strength (two species; 0 = off)
+    int nc_hmax = 0;    // near-contact probe range (nodes)
+    void *scratch_nc = nullptr;  // near-contact force (3 N reals), then the moment scheme's phase field (N)
     int nfields = 0;  // stored arrays per state copy
     size_t elem = 4;  // bytes per stored element
     int64_t state_elems = 0;  // elements per state copy (blocked moment layout or q x N populations)
@@ -73,6 +76,11 @@ hipError_t launch_cg_adjoint_step(const lbm_ctx *c, const void *state, const voi
 // Co-state (real type of the context, nfields fields) between the public
 // layout (nfields x N) and the stored blocked layout (state_elems elements).
 hipError_t launch_costate_convert(const lbm_ctx *c, const void *src, void *dst, bool to_stored);
+
+// Near-contact force of the two-species schemes into c->scratch_nc (three
+// arrays of N), from the phase field `phi` (N values, population scheme) or,
+// if phi is NULL, from the moment state `moments`.
+hipError_t launch_nc_force(const lbm_ctx *c, const void *moments, const void *phi);
 
 // Population scheme in place (AA pattern) on the single array `state`; odd:
 // the state has gone through an odd number of steps.

@@ -204,10 +204,12 @@ __global__ __launch_bounds__(256) void k_pop_cg_phi(const float *__restrict__ in
     phi[n] = (r1 - r2) / (r1 + r2);
 }
 
-template <int Q>
+// FORCE: a body force (three arrays of N values) enters with Guo's forcing
+// (equilibrium at u* = (j + F/2)/rho, source (1 - omega/2) S_i).
+template <int Q, bool FORCE>
 __global__ __launch_bounds__(256) void k_pop_cg_step(const float *__restrict__ in, float *__restrict__ out,
                                                      const float *__restrict__ phi, int nx, int ny, int nz, int64_t N,
-                                                     float omega, float A, float beta)
+                                                     float omega, float A, float beta, const float *__restrict__ frc)
 {
     using L = Lattice<Q>;
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -244,7 +246,17 @@ __global__ __launch_bounds__(256) void k_pop_cg_step(const float *__restrict__ i
     const float G2 = fma_(Gx, Gx, fma_(Gy, Gy, Gz * Gz));
     const float invD = 1.0f / __builtin_sqrtf(G2 + 1e-6f);
     const float inv_rho = reciprocal<float>(rho);
-    const float ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
+    float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+    if (FORCE) {
+        Fx = frc[n];
+        Fy = frc[N + n];
+        Fz = frc[2 * N + n];
+    }
+    const float ux = FORCE ? fma_(0.5f, Fx, jx) * inv_rho : jx * inv_rho;
+    const float uy = FORCE ? fma_(0.5f, Fy, jy) * inv_rho : jy * inv_rho;
+    const float uz = FORCE ? fma_(0.5f, Fz, jz) * inv_rho : jz * inv_rho;
+    const float uF = fma_(ux, Fx, fma_(uy, Fy, uz * Fz));
+    const float src = 1.0f - 0.5f * omega;
     const float uu = fma_(ux, ux, fma_(uy, uy, uz * uz));
     const float s1 = r1 * inv_rho, s2 = r2 * inv_rho;
     const float C = beta * r1 * r2 * inv_rho;
@@ -266,7 +278,11 @@ __global__ __launch_bounds__(256) void k_pop_cg_step(const float *__restrict__ i
         const float feq = w * rho * fma_(4.5f, cu * cu, fma_(3.0f, cu, 1.0f - 1.5f * uu));
         const float cG = (float)cx * Gx + (float)cy * Gy + (float)cz * Gz;
         const float df = 0.5f * A * fma_(w, cG * cG, -w * G2) * invD;
-        const float fp = fma_(omega, feq - f[i], f[i]) + df;
+        float fp = fma_(omega, feq - f[i], f[i]) + df;
+        if (FORCE) {
+            const float cF = (float)cx * Fx + (float)cy * Fy + (float)cz * Fz;
+            fp = fma_(src * w, fma_(9.0f * cu, cF, 3.0f * (cF - uF)), fp);
+        }
         const float inv_c = (float)(1.0 / __builtin_sqrt((double)(cx * cx + cy * cy + cz * cz)));
         const float rc = C * w * inv_c * (cG * invD);
         const float o1 = fma_(s1, fp, rc), o2 = fma_(s2, fp, -rc);
@@ -285,9 +301,18 @@ hipError_t run_cg(const lbm_ctx *c, const void *in, void *out)
     const int64_t blocks = (c->N + 255) / 256;
     hipLaunchKernelGGL((k_pop_cg_phi<Q>), dim3((unsigned)blocks), dim3(256), 0, c->stream,
                        static_cast<const float *>(in), c->scratch_phi, c->nx, c->ny, c->nz, c->N);
-    hipLaunchKernelGGL((k_pop_cg_step<Q>), dim3((unsigned)blocks), dim3(256), 0, c->stream,
-                       static_cast<const float *>(in), static_cast<float *>(out), c->scratch_phi, c->nx, c->ny,
-                       c->nz, c->N, (float)c->omega, (float)c->A, (float)c->beta);
+    if (c->nc_A != 0.0) {
+        hipError_t e = launch_nc_force(c, nullptr, c->scratch_phi);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_pop_cg_step<Q, true>), dim3((unsigned)blocks), dim3(256), 0, c->stream,
+                           static_cast<const float *>(in), static_cast<float *>(out), c->scratch_phi, c->nx, c->ny,
+                           c->nz, c->N, (float)c->omega, (float)c->A, (float)c->beta,
+                           static_cast<const float *>(c->scratch_nc));
+    } else {
+        hipLaunchKernelGGL((k_pop_cg_step<Q, false>), dim3((unsigned)blocks), dim3(256), 0, c->stream,
+                           static_cast<const float *>(in), static_cast<float *>(out), c->scratch_phi, c->nx, c->ny,
+                           c->nz, c->N, (float)c->omega, (float)c->A, (float)c->beta, nullptr);
+    }
     return hipGetLastError();
 }
 

@@ -27,7 +27,8 @@ class LBM:
     def __init__(self, shape, lattice: int = 19, tau: float = 0.8, species: int = 1, *,
                  scheme: str = "moment", storage: str = "f32", beta: float = 0.7, sigma: float = 0.01,
                  s_pi: float = 0.0, device: int = 0, stream: torch.cuda.Stream | None = None,
-                 check_every: int = 0, split: bool = False, steps_per_sweep: int = 0):
+                 check_every: int = 0, split: bool = False, steps_per_sweep: int = 0, nc_A: float = 0.0,
+                 nc_hmax: int = 0):
         lib = _lib.load()
         self.nx, self.ny, self.nz = (int(s) for s in shape)
         self.q, self.tau, self.species = int(lattice), float(tau), int(species)
@@ -47,6 +48,8 @@ class LBM:
         opts.check_every = check_every
         opts.split = int(bool(split))
         opts.steps_per_sweep = int(steps_per_sweep)
+        opts.nc_A = float(nc_A)
+        opts.nc_hmax = int(nc_hmax)
         ctx = ctypes.c_void_p()
         rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(self.nx, self.ny, self.nz), self.q, self.tau,
                             self.species, ctypes.byref(opts))

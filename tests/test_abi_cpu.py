@@ -100,3 +100,21 @@ def test_create_rejects_bad_sweep_before_device(species, scheme, storage, split,
     rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(8, 8, 8), 19, 0.8, species, ctypes.byref(opts))
     assert rc == _lib.LBM_EINVAL
     assert not ctx.value
+
+
+@pytest.mark.parametrize("species,A,hmax", [
+    (1, 0.01, 4),            # two species only
+    (2, 0.01, 0),            # 1 <= nc_hmax <= 32
+    (2, 0.01, 33),
+    (2, float("nan"), 4),
+])
+def test_create_rejects_bad_near_contact_before_device(species, A, hmax):
+    lib = _lib.load()
+    opts = _lib.Opts()
+    lib.lbm_default_opts(ctypes.byref(opts))
+    assert opts.nc_A == 0.0 and opts.nc_hmax == 0
+    opts.nc_A, opts.nc_hmax = A, hmax
+    ctx = ctypes.c_void_p(123)
+    rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(8, 8, 8), 19, 0.8, species, ctypes.byref(opts))
+    assert rc == _lib.LBM_EINVAL
+    assert not ctx.value

@@ -1,0 +1,89 @@
+"""GPU parity of the near-contact force (the LBNCI term of Sec. III.C, under
+the readings stated in csrc/nc_force.hip and the oracle) for both
+two-component schemes, against the FP64 oracle: two drops whose interfaces
+are a few nodes apart, so that films are found by the probes."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2301_01622_amd import inputs as I  # noqa: E402
+
+TAU, SIGMA, BETA = 0.8, 0.01, 0.7
+AH, HMAX = 0.05, 4
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def LBM():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2301_01622_amd.lbm import LBM as _LBM
+    return _LBM
+
+
+def _contact_state(oracle, shape, gap=3.0, R=5.0):
+    nz, ny, nx = shape
+    c1 = (nx / 2 - gap / 2 - R, ny / 2 + 0.3, nz / 2 - 0.2)
+    c2 = (nx / 2 + gap / 2 + R, ny / 2 - 0.4, nz / 2 + 0.1)
+    r1, r2, u = I.droplets(shape, centres=[c1, c2], radius=R, velocities=[(0.02, 0, 0), (-0.02, 0, 0)], width=1.0)
+    return np.ascontiguousarray(oracle.equilibrium_moments2(r1, r2, u)), r1
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_near_contact_moment_scheme_matches_oracle(LBM, oracle, q, storage, tol):
+    shape = (14, 17, 31)
+    _say(f"near-contact moment scheme {shape} D3Q{q} {storage} 6 steps")
+    H, r1 = _contact_state(oracle, shape)
+    F, h = oracle.nc_force(2 * r1 - 1, q, AH, HMAX)
+    assert (h > 0).sum() > 20  # films are found between the drops
+    A = oracle.sigma_to_A(SIGMA, TAU)
+    ref = oracle.cg_moment_run(H, q, TAU, A, BETA, 6, Ah=AH, hmax=HMAX)
+    free = oracle.cg_moment_run(H, q, TAU, A, BETA, 6)
+    assert np.abs(ref - free).max() > 1e-4  # the force matters
+    nf, nz, ny, nx = H.shape
+    sim = LBM((nx, ny, nz), q, TAU, species=2, storage=storage, sigma=SIGMA, beta=BETA, nc_A=AH, nc_hmax=HMAX)
+    sim.set_moments(torch.from_numpy(H).cuda())
+    sim.step(6)
+    got = sim.get_moments(torch.float64).cpu().numpy()
+    sim.close()
+    err = np.abs(got - ref).max(axis=(1, 2, 3))
+    _say(f"  max err per field {err}")
+    assert err.max() <= tol
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_near_contact_population_scheme_matches_oracle(LBM, oracle, q):
+    shape = (14, 17, 31)
+    _say(f"near-contact population scheme {shape} D3Q{q} f32 6 steps")
+    H, _ = _contact_state(oracle, shape)
+    A = oracle.sigma_to_A(SIGMA, TAU)
+    f1, f2 = oracle.cg_populations_from_moments(H, q)
+    g1, g2 = oracle.cg_population_run(f1, f2, q, TAU, A, BETA, 6, Ah=AH, hmax=HMAX)
+    ref = oracle.cg_moments_from_populations(g1, g2, q)
+    nf, nz, ny, nx = H.shape
+    sim = LBM((nx, ny, nz), q, TAU, species=2, storage="f32", sigma=SIGMA, beta=BETA, scheme="population",
+              nc_A=AH, nc_hmax=HMAX)
+    sim.set_moments(torch.from_numpy(H).cuda())
+    sim.step(6)
+    got = sim.get_moments(torch.float64).cpu().numpy()
+    sim.close()
+    err = np.abs(got - ref).max(axis=(1, 2, 3))
+    _say(f"  max err per field {err}")
+    assert err.max() <= 5e-6
+
+
+def test_near_contact_rejects_adjoint(LBM):
+    import ctypes
+    from paper_2301_01622_amd import _lib
+    sim = LBM((8, 8, 8), 19, TAU, species=2, storage="f32", sigma=SIGMA, beta=BETA, nc_A=AH, nc_hmax=HMAX)
+    st = sim.new_checkpoint()
+    lam, lo = sim.new_costate(), sim.new_costate()
+    p = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    assert sim._lib.lbm_adjoint_step_stored(sim._ctx, p(st), p(lam), p(lo), None) == _lib.LBM_ESTATE
+    sim.close()

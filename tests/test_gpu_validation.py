@@ -1,9 +1,11 @@
-"""The paper's validation experiment (two drops of diameter 30 on 128^3,
-coalescing off-axis collision) with the moment scheme and the population
-colour-gradient LB side by side on the GPU.  The paper's curves are not
-available, so the bounds are sanity bounds (about five times what the full
-8000-step runs give: 3.7e-4 for <rho1>, 2.8e-3 at the probes); the run here
-is 2000 steps."""
+"""The paper's validation experiment (two drops of diameter 30 on 128^3) with
+the moment scheme and the population colour-gradient LB side by side on the
+GPU: a head-on collision with the near-contact force (A_h = 0.01: a film
+keeps the drops apart, the phase field at the box centre stays negative) and
+without it (A_h = 0: they merge, phi there goes to +1).  The paper's curves
+are not available, so the bounds on the differences between the schemes are
+sanity bounds, about five times what the runs give (2000 steps here; the
+8000-step figures are reported with the design notes)."""
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -11,14 +13,20 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def test_moment_and_population_schemes_agree_on_droplet_collision():
+@pytest.mark.parametrize("case,merges", [("head_on", False), ("head_on_coalescence", True)])
+def test_moment_and_population_schemes_agree_on_droplet_collision(case, merges):
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     from paper_2301_01622_amd import validation
-    print("[gpu] validation off_axis 128^3, 2000 steps", flush=True)
-    res = validation.run("off_axis", steps=2000, every=250)
+    print(f"[gpu] validation {case} 128^3, 2000 steps", flush=True)
+    res = validation.run(case, steps=2000, every=250)
     s = res["summary"]
     print(f"[gpu]   {s}", flush=True)
-    assert s["max_rel_diff_mean_rho1"] <= 2e-3
-    assert max(s["max_probe_rel_diff"].values()) <= 1e-2
+    assert s["max_rel_diff_mean_rho1"] <= 5e-3
+    assert max(s["max_probe_rel_diff"].values()) <= 0.1
     # far from the drops both schemes see undisturbed fluid
     assert s["max_probe_rel_diff"]["far"] <= 1e-6
+    for scheme in ("moment", "population"):
+        if merges:
+            assert s["max_phi_centre"][scheme] > 0.9
+        else:
+            assert s["max_phi_centre"][scheme] < 0.0
