@@ -226,6 +226,8 @@ def main() -> int:
     ap.add_argument("--no-population", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-two-component", action="store_true")
+    ap.add_argument("--steps-per-sweep", type=int, default=STEPS_PER_LAUNCH, choices=(1, 2),
+                    help="steps per launch of the measured path (1: the one-step kernel and one-step adjoint)")
     ap.add_argument("--calibrate-copy", type=int, default=10,
                     help="also time this many state copies (plain copy kernel of known size)")
     args = ap.parse_args()
@@ -251,7 +253,8 @@ def main() -> int:
         ms1 = time_steps(s1, stream, args.steps, args.warmup)
         s1.close()
 
-        sim = LBM((n, n, n), q, tau, storage="f32", stream=stream, steps_per_sweep=STEPS_PER_LAUNCH)
+        spl = args.steps_per_sweep
+        sim = LBM((n, n, n), q, tau, storage="f32", stream=stream, steps_per_sweep=spl)
         sim.set_equilibrium(rho_d, u_d)
         ms = time_steps(sim, stream, args.steps, args.warmup)
         state_bytes, step_bytes = sim.memory_info()
@@ -332,9 +335,9 @@ def main() -> int:
     mlups = N / (ms * 1e-3) / 1e6
     # Roofline of the sweep kernel: algorithmic bytes per launch (80 B per node
     # and step, two steps) over the launch time (two steps).
-    launch_ms = STEPS_PER_LAUNCH * ms
-    achieved = STEPS_PER_LAUNCH * step_bytes / (launch_ms * 1e-3) / 1e9
-    traffic_bytes = measured_traffic(N)
+    launch_ms = spl * ms
+    achieved = spl * step_bytes / (launch_ms * 1e-3) / 1e9
+    traffic_bytes = measured_traffic(N) if spl == STEPS_PER_LAUNCH else None
     line = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -357,15 +360,15 @@ def main() -> int:
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_moment_sweep2 (two steps per launch)",
+            "kernel": "k_moment_sweep2 (two steps per launch)" if spl == 2 else "k_moment_tile (one step per launch)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": round(traffic_bytes / (launch_ms * 1e-3) / 1e9, 1) if traffic_bytes else None,
-            "steps_per_launch": STEPS_PER_LAUNCH,
+            "steps_per_launch": spl,
             "ms_per_launch": round(launch_ms, 5),
-            "algorithmic_bytes_per_launch": STEPS_PER_LAUNCH * step_bytes,
+            "algorithmic_bytes_per_launch": spl * step_bytes,
             "note": "algorithmic bytes are those of the step (every moment read and written once per node and "
                     "step, 80 B); the sweep carries each tile through two steps and moves the state once per "
                     "launch, so the HBM traffic it causes ('traffic') is about half of 'achieved': the kernel is "
@@ -383,7 +386,7 @@ def main() -> int:
     }
     if traffic_bytes:
         line["roofline"]["traffic_bytes_per_launch"] = traffic_bytes
-        line["roofline"]["traffic_over_algorithmic"] = round(traffic_bytes / (STEPS_PER_LAUNCH * step_bytes), 4)
+        line["roofline"]["traffic_over_algorithmic"] = round(traffic_bytes / (spl * step_bytes), 4)
     line["adjoint"] = adjoint
     line["split_approach"] = split
     if two:
