@@ -172,6 +172,7 @@ __global__ __launch_bounds__((kSweepThreads<IX, IY>)) void k_moment_sweep2(const
     // p-1, second-step plane p-2.
     auto plane_step = [&](int p, Moments<R> &m) {
         R own0[3], own1[3];
+        S vm[10];  // the intermediate state, stored after the second barrier (MID)
         if (r0) publish(collide_node(m), p0, N0, h0, own0);
         __syncthreads();
         if (p + 2 <= z_end + 1) fetch(p + 2, m);
@@ -182,13 +183,8 @@ __global__ __launch_bounds__((kSweepThreads<IX, IY>)) void k_moment_sweep2(const
             pull_layer(std::integral_constant<int, 1>(), p0, N0, HX0, h0, own0[2], a1[2]);
             // Intermediate plane p-1 has received from p-2, p-1 and p.
             if (p >= z0) {
-                S v[10];
+                S *v = vm;
                 stored_values(a1[0], v);
-                if (MID && active && p - 1 >= z0 && p - 1 < z_end) {
-                    const int64_t o = dst_xy + (int64_t)(p - 1) * plane;
-#pragma unroll
-                    for (int k = 0; k < 10; ++k) store_out(mid + k * kBlock + o, v[k]);
-                }
                 Moments<R> mi;
 #pragma unroll
                 for (int k = 0; k < 10; ++k) mi.v[k] = Store<S>::load(v[k]);
@@ -212,6 +208,11 @@ __global__ __launch_bounds__((kSweepThreads<IX, IY>)) void k_moment_sweep2(const
                 const int64_t o = dst_xy + (int64_t)d * plane;
 #pragma unroll
                 for (int k = 0; k < 10; ++k) store_out(out + k * kBlock + o, v[k]);
+            }
+            if (MID && active && p - 1 >= z0 && p - 1 < z_end) {
+                const int64_t o = dst_xy + (int64_t)(p - 1) * plane;
+#pragma unroll
+                for (int k = 0; k < 10; ++k) store_out(mid + k * kBlock + o, vm[k]);
             }
             a2[0] = a2[1];
             a2[1] = a2[2];
