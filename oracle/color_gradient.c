@@ -48,6 +48,10 @@
  *             u* = (j + F/2)/rho, and (1 - omega/2) S_i is added with
  *             S_i = w_i [(c_i - u*).F / c_s^2 + (c_i.u*)(c_i.F) / c_s^4];
  *             the stored momentum of the next step gains F.
+ *   The paper prints no near-contact values, so these readings are parity
+ *   unpinned as readings; what they compute is pinned (film distances and
+ *   forces between flat slabs in closed form, the forced collision's moments,
+ *   momentum gain equal to the total force).
  *
  * Without populations the perturbation enters through its second moment
  * only: the collided tensor is P' = P^eq + (1-omega)(P - P^eq) + DP and the
