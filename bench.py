@@ -226,6 +226,7 @@ def main() -> int:
     ap.add_argument("--no-population", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-two-component", action="store_true")
+    ap.add_argument("--no-reduced-precision", action="store_true")
     ap.add_argument("--steps-per-sweep", type=int, default=STEPS_PER_LAUNCH, choices=(1, 2),
                     help="steps per launch of the measured path (1: the one-step kernel and one-step adjoint)")
     ap.add_argument("--calibrate-copy", type=int, default=10,
@@ -332,6 +333,28 @@ def main() -> int:
     if not args.no_two_component:
         two = two_component(args.steps // 4 or 1, args.warmup)
 
+    # Reduced-precision storage on 512^3 D3Q27 (tau = 0.55, shear wave plus
+    # solenoidal noise): FP16 and BF16 moments, FP32 arithmetic.
+    reduced = None
+    if not args.no_reduced_precision:
+        reduced = {"workload": "512^3 periodic box, D3Q27, tau=0.55, u_x = 0.01 sin(2 pi y/512) + solenoidal noise "
+                               "1e-4 (seed 16220004), 16-bit moments (rho-1, j, S scaled), FP32 arithmetic"}
+        rho5, u5 = inputs.shear_wave_with_noise(512, seed=inputs.SEED_C4, u0=0.01, noise=1e-4)
+        r5, v5 = torch.from_numpy(rho5).cuda(), torch.from_numpy(u5).cuda()
+        del rho5, u5
+        rs = torch.cuda.Stream()
+        with torch.cuda.stream(rs):
+            for st in ("f16", "bf16"):
+                sm = LBM((512, 512, 512), q, 0.55, storage=st, stream=rs)
+                sm.set_equilibrium(r5, v5)
+                t = time_steps(sm, rs, max(args.steps // 10, 2), 4)
+                b_state, b_step = sm.memory_info()
+                sm.close()
+                reduced[st] = {"value": round(512 ** 3 / (t * 1e-3) / 1e6, 1), "unit": "MLUPS",
+                               "ms_per_step": round(t, 5), "bytes_per_node_state": b_state // 512 ** 3,
+                               "bytes_per_node_step": b_step // 512 ** 3}
+        del r5, v5
+
     mlups = N / (ms * 1e-3) / 1e6
     # Roofline of the sweep kernel: algorithmic bytes per launch (80 B per node
     # and step, two steps) over the launch time (two steps).
@@ -391,6 +414,8 @@ def main() -> int:
     line["split_approach"] = split
     if two:
         line["two_component"] = two
+    if reduced:
+        line["reduced_precision_storage"] = reduced
     if copy:
         line["roofline"]["frac_of_measured_copy"] = round(achieved / copy["gbs"], 4)
         line["single_step_kernel"]["frac_of_measured_copy"] = round(step_bytes / (ms1 * 1e-3) / 1e9 / copy["gbs"], 4)
