@@ -101,8 +101,8 @@ typedef struct {
     int steps_per_sweep; /* time steps lbm_step applies per pass over the state: 1, or 2 (two
                         steps carried through each tile in one pass, the state read and written
                         once per two steps; results equal single steps bit for bit).  2 needs
-                        one species, the moment scheme, the fused step and FP32/FP16/BF16
-                        storage (else LBM_EINVAL).  0 (default): 2 where available, else 1.
+                        one species, the moment scheme, the fused step, FP32/FP16/BF16
+                        storage and one stored xy-plane below 2 GiB (else LBM_EINVAL).  0 (default): 2 where available, else 1.
                         lbm_step falls back to single steps for an odd remainder and where
                         a check_every health check falls between the two steps */
     double nc_A;     /* near-contact force of the LBNCI extension (Sec. III.C), two species:

@@ -66,6 +66,24 @@ __device__ __forceinline__ void adjoint_layer2(const R *l, Layer<R> &o)
 template <int IX, int IY>
 constexpr int kAdjSweepThreads = ((IX + 4) * (IY + 4) + 63) / 64 * 64;
 
+// Buffer addressing of one z-plane (as in the forward sweep): descriptor in
+// scalar registers, 32-bit node offset, field offset as an immediate.  The
+// plane is below 2 GiB wherever the two-step passes are enabled.
+template <class T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc2(const T *p, int64_t plane)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(p), (short)0, (int)(plane * (int64_t)sizeof(T)),
+                                             0x00020000);
+}
+template <class T>
+__device__ __forceinline__ T load_field2(__amdgpu_buffer_rsrc_t rs, uint32_t vo, int k)
+{
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, k * kBlock * 4, 0));
+    else if constexpr (sizeof(T) == 2)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rs, vo, k * kBlock * 2, 0));
+}
+
 // Position (x, y) of the m-th node of the one-node-wide ring of a W x H
 // rectangle: top row, bottom row, left column, right column.
 __device__ __forceinline__ void ring_pos2(int m, int W, int H, int &x, int &y)
@@ -126,19 +144,20 @@ __global__ __launch_bounds__((kAdjSweepThreads<IX, IY>)) void k_adjoint_sweep2(
     auto wrapz = [&](int p) { return p < 0 ? p + g.nz : (p >= g.nz ? p - g.nz : p); };
 
     R la[10];  // lam(t+1) of the source plane; the next plane's loads are issued after publishing
+    const uint32_t vo_r = (uint32_t)node_xy * (uint32_t)sizeof(R), vo_s = (uint32_t)node_xy * (uint32_t)sizeof(S);
     auto fetch = [&](int p, R *l) {
         if (!r0) return;
-        const int64_t o = node_xy + (int64_t)wrapz(p) * plane;
+        const __amdgpu_buffer_rsrc_t rs = plane_rsrc2(lam_in + (int64_t)wrapz(p) * plane, plane);
 #pragma unroll
-        for (int k = 0; k < 10; ++k) l[k] = lam_in[k * kBlock + o];
+        for (int k = 0; k < 10; ++k) l[k] = load_field2<R>(rs, vo_r, k);
     };
     // Forward states for the node-local maps, loaded one plane ahead:
     // M(t) of R1 nodes and M(t-1) of interior nodes.
     S st1[10], st0[10];
     auto fetch_state = [&](const S *st, int d, S *v) {
-        const int64_t o = node_xy + (int64_t)wrapz(d) * plane;
+        const __amdgpu_buffer_rsrc_t rs = plane_rsrc2(st + (int64_t)wrapz(d) * plane, plane);
 #pragma unroll
-        for (int k = 0; k < 10; ++k) v[k] = st[k * kBlock + o];
+        for (int k = 0; k < 10; ++k) v[k] = load_field2<S>(rs, vo_s, k);
     };
 
     auto publish = [&](const R *l, R *P, int n, int h, R *own) {
@@ -245,9 +264,11 @@ __global__ __launch_bounds__((kAdjSweepThreads<IX, IY>)) void k_adjoint_sweep2(
                 if (d + 1 < z_end) fetch_state(state_t0, d + 1, st0);
                 if (active) {
                     dom += e;
-                    const int64_t o = node_xy + (int64_t)d * plane;
+                    const __amdgpu_buffer_rsrc_t rs = plane_rsrc2(lam_out + (int64_t)d * plane, plane);
 #pragma unroll
-                    for (int k = 0; k < 10; ++k) store_out(lam_out + k * kBlock + o, lo[k]);
+                    for (int k = 0; k < 10; ++k)
+                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, lo[k]), rs, vo_r,
+                                                              k * kBlock * 4, 2);
                 }
             }
             a2[0] = a2[1];

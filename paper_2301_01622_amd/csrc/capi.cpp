@@ -152,7 +152,11 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     if (o.nc_A != 0.0 && (species != 2 || !std::isfinite(o.nc_A) || o.nc_hmax < 1 || o.nc_hmax > 32))
         return LBM_EINVAL;
     // Two-step sweeps: one species, fused moment step, not FP64 storage.
-    const bool sweep2_ok = o.scheme == LBM_SCHEME_MOMENT && species == 1 && o.split == 0 && o.storage != LBM_STORE_F64;
+    // The sweep addresses one z-plane (at most 2 GiB) per buffer descriptor.
+    const bool sweep2_ok = o.scheme == LBM_SCHEME_MOMENT && species == 1 && o.split == 0 &&
+                           o.storage != LBM_STORE_F64 &&
+                           lbm::moment_layout(grid.nx, grid.ny, 10).plane * (int64_t)storage_bytes(o.storage) <
+                               ((int64_t)1 << 31);
     if (o.steps_per_sweep < 0 || o.steps_per_sweep > 2 || (o.steps_per_sweep == 2 && !sweep2_ok)) return LBM_EINVAL;
     const int sweep = o.steps_per_sweep == 0 ? (sweep2_ok ? 2 : 1) : o.steps_per_sweep;
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
