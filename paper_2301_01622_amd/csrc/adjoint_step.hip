@@ -22,6 +22,7 @@
 
 #include <type_traits>
 
+#include "adjoint_math.hpp"
 #include "internal.hpp"
 #include "moment_math.hpp"
 #include "storage.hpp"
@@ -29,38 +30,6 @@
 
 namespace lbm {
 namespace {
-
-// b = w_i (lam_rho + c.lam_j + c c : lam_P) for the nine slots of layer CZ
-// (stored off-diagonal components enter once: m_i has c_x c_y for P_xy).
-template <int Q, int CZ, class R>
-__device__ __forceinline__ void adjoint_layer(const R *l, Layer<R> &o)
-{
-    // l: rho, jx, jy, jz, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz
-    R A, Bx, By;
-    if (CZ == 0) {
-        A = l[0];
-        Bx = l[1];
-        By = l[2];
-    } else {
-        A = (CZ > 0 ? l[0] + l[3] : l[0] - l[3]) + l[6];
-        Bx = CZ > 0 ? l[1] + l[8] : l[1] - l[8];
-        By = CZ > 0 ? l[2] + l[9] : l[2] - l[9];
-    }
-    const R Px = A + l[4], Py = A + l[5];
-    o.v[4] = R(weight<Q>(0, 0, CZ)) * A;
-    o.v[5] = R(weight<Q>(1, 0, CZ)) * (Px + Bx);
-    o.v[3] = R(weight<Q>(-1, 0, CZ)) * (Px - Bx);
-    o.v[7] = R(weight<Q>(0, 1, CZ)) * (Py + By);
-    o.v[1] = R(weight<Q>(0, -1, CZ)) * (Py - By);
-    if (has_dir<Q>(1, 1, CZ)) {
-        const R Pxy = Px + l[5];
-        const R D1 = Pxy + l[7], D2 = Pxy - l[7], E1 = Bx + By, E2 = Bx - By;
-        o.v[8] = R(weight<Q>(1, 1, CZ)) * (D1 + E1);
-        o.v[0] = R(weight<Q>(-1, -1, CZ)) * (D1 - E1);
-        o.v[2] = R(weight<Q>(1, -1, CZ)) * (D2 + E2);
-        o.v[6] = R(weight<Q>(-1, 1, CZ)) * (D2 - E2);
-    }
-}
 
 // LSTORED: co-states in the stored (blocked) layout of the state instead of
 // the public one.
@@ -167,41 +136,13 @@ __global__ __launch_bounds__(TX *TY) void k_adjoint_tile(const S *__restrict__ s
     auto finish = [&](int d) {
         const int64_t so = g.lay.xy(x0 + lx, y0 + ly) + (int64_t)d * g.lay.plane;  // stored
         const int64_t o = LSTORED ? so : (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)d * plane;
-        const MomentAcc<R> &a = acc[0];
-        const R dr = Store<S>::load(state[so]);
-        const R jx = Store<S>::load(state[kBlock + so]), jy = Store<S>::load(state[2 * kBlock + so]),
-                jz = Store<S>::load(state[3 * kBlock + so]);
-        R s[6];
+        S v[10];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) s[k] = Store<S>::load(state[(4 + k) * kBlock + so]) * inv_s_pi;
-        const R inv_rho = R(1) / (R(1) + dr);
-        // Gamma = 4.5 sum w c c a - 1.5 alpha I
-        const R gxx = fma_(R(4.5), a.mxx, R(-1.5) * a.r), gyy = fma_(R(4.5), a.myy, R(-1.5) * a.r),
-                gzz = fma_(R(4.5), a.mzz, R(-1.5) * a.r);
-        const R gxy = R(4.5) * a.mxy, gxz = R(4.5) * a.mxz, gyz = R(4.5) * a.myz;
-        const R Gjx = fma_(gxx, jx, fma_(gxy, jy, gxz * jz));
-        const R Gjy = fma_(gxy, jx, fma_(gyy, jy, gyz * jz));
-        const R Gjz = fma_(gxz, jx, fma_(gyz, jy, gzz * jz));
-        const R jGj = fma_(jx, Gjx, fma_(jy, Gjy, jz * Gjz));
-        const R om1 = R(1) - omega;
-        const R tr = (gxx + gyy) + gzz;
-        lam_out[o] = fma_(-omega * inv_rho * inv_rho, jGj, fma_(-om1 * R(1.0 / 3.0), tr, a.r));
-        const R two_om = R(2) * omega * inv_rho;
-        lam_out[LF + o] = fma_(two_om, Gjx, R(3) * a.jx);
-        lam_out[2 * LF + o] = fma_(two_om, Gjy, R(3) * a.jy);
-        lam_out[3 * LF + o] = fma_(two_om, Gjz, R(3) * a.jz);
-        lam_out[4 * LF + o] = om1 * gxx;
-        lam_out[5 * LF + o] = om1 * gyy;
-        lam_out[6 * LF + o] = om1 * gzz;
-        lam_out[7 * LF + o] = R(2) * om1 * gxy;
-        lam_out[8 * LF + o] = R(2) * om1 * gxz;
-        lam_out[9 * LF + o] = R(2) * om1 * gyz;
-        // Gamma : (j j/rho - S)
-        const double e = (double)(gxx * (jx * jx * inv_rho - s[0]) + gyy * (jy * jy * inv_rho - s[1]) +
-                                  gzz * (jz * jz * inv_rho - s[2])) +
-                         2.0 * (double)(gxy * (jx * jy * inv_rho - s[3]) + gxz * (jx * jz * inv_rho - s[4]) +
-                                        gyz * (jy * jz * inv_rho - s[5]));
-        dom += e;
+        for (int k = 0; k < 10; ++k) v[k] = state[k * kBlock + so];
+        R lam[10];
+        dom += adjoint_node<S>(acc[0], v, omega, inv_s_pi, lam);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) lam_out[k * LF + o] = lam[k];
     };
 
     auto plane_step = [&](int p, R *own, R *ring) {

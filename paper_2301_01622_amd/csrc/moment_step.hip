@@ -108,10 +108,7 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
             return collided_from<R>(v.v[0], v.v[1], v.v[2], v.v[3], v.v[4] * sc, v.v[5] * sc, v.v[6] * sc,
                                     v.v[7] * sc, v.v[8] * sc, v.v[9] * sc);
         }
-        if (kScaled)
-            return collide<R>(v.v[0], v.v[1], v.v[2], v.v[3], v.v[4] * inv_s_pi, v.v[5] * inv_s_pi,
-                              v.v[6] * inv_s_pi, v.v[7] * inv_s_pi, v.v[8] * inv_s_pi, v.v[9] * inv_s_pi, omega);
-        return collide<R>(v.v[0], v.v[1], v.v[2], v.v[3], v.v[4], v.v[5], v.v[6], v.v[7], v.v[8], v.v[9], omega);
+        return collide_stored<S>(v, omega, inv_s_pi);
     };
 
     // Writes the populations of one source node into LDS slot h; returns the
@@ -164,19 +161,10 @@ __global__ __launch_bounds__(TX *TY) void k_moment_tile(const S *__restrict__ in
         const int d = p - 1;
         if (d >= z0 && active) {
             const int64_t o = g.lay.xy(x0 + lx, y0 + ly) + (int64_t)d * plane;
-            const MomentAcc<R> &a = acc[0];
-            const R m3 = R(-1.0 / 3.0);
-            const R sc = kScaled ? s_pi : R(1);
-            store_out(out + o, Store<S>::make(a.r));
-            store_out(out + kBlock + o, Store<S>::make(a.jx));
-            store_out(out + 2 * kBlock + o, Store<S>::make(a.jy));
-            store_out(out + 3 * kBlock + o, Store<S>::make(a.jz));
-            store_out(out + 4 * kBlock + o, Store<S>::make(kScaled ? fma_(m3, a.r, a.mxx) * sc : fma_(m3, a.r, a.mxx)));
-            store_out(out + 5 * kBlock + o, Store<S>::make(kScaled ? fma_(m3, a.r, a.myy) * sc : fma_(m3, a.r, a.myy)));
-            store_out(out + 6 * kBlock + o, Store<S>::make(kScaled ? fma_(m3, a.r, a.mzz) * sc : fma_(m3, a.r, a.mzz)));
-            store_out(out + 7 * kBlock + o, Store<S>::make(kScaled ? a.mxy * sc : a.mxy));
-            store_out(out + 8 * kBlock + o, Store<S>::make(kScaled ? a.mxz * sc : a.mxz));
-            store_out(out + 9 * kBlock + o, Store<S>::make(kScaled ? a.myz * sc : a.myz));
+            S v[10];
+            stored_moments<S>(acc[0], s_pi, v);
+#pragma unroll
+            for (int k = 0; k < 10; ++k) store_out(out + k * kBlock + o, v[k]);
         }
         acc[0] = acc[1];
         acc[1] = acc[2];

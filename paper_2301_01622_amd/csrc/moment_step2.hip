@@ -145,28 +145,8 @@ __global__ __launch_bounds__((kSweepThreads<IX, IY>)) void k_moment_sweep2(const
         for (int k = 0; k < 10; ++k) m.v[k] = Store<S>::load(load_field<S>(rs, vo, k));
     };
 
-    auto collide_node = [&](const Moments<R> &v) {
-        if (kScaled)
-            return collide<R>(v.v[0], v.v[1], v.v[2], v.v[3], v.v[4] * inv_s_pi, v.v[5] * inv_s_pi,
-                              v.v[6] * inv_s_pi, v.v[7] * inv_s_pi, v.v[8] * inv_s_pi, v.v[9] * inv_s_pi, omega);
-        return collide<R>(v.v[0], v.v[1], v.v[2], v.v[3], v.v[4], v.v[5], v.v[6], v.v[7], v.v[8], v.v[9], omega);
-    };
-
-    // The 10 values a finished accumulator is stored as (stored format).
-    auto stored_values = [&](const MomentAcc<R> &a, S *v) {
-        const R m3 = R(-1.0 / 3.0);
-        const R sc = kScaled ? s_pi : R(1);
-        v[0] = Store<S>::make(a.r);
-        v[1] = Store<S>::make(a.jx);
-        v[2] = Store<S>::make(a.jy);
-        v[3] = Store<S>::make(a.jz);
-        v[4] = Store<S>::make(kScaled ? fma_(m3, a.r, a.mxx) * sc : fma_(m3, a.r, a.mxx));
-        v[5] = Store<S>::make(kScaled ? fma_(m3, a.r, a.myy) * sc : fma_(m3, a.r, a.myy));
-        v[6] = Store<S>::make(kScaled ? fma_(m3, a.r, a.mzz) * sc : fma_(m3, a.r, a.mzz));
-        v[7] = Store<S>::make(kScaled ? a.mxy * sc : a.mxy);
-        v[8] = Store<S>::make(kScaled ? a.mxz * sc : a.mxz);
-        v[9] = Store<S>::make(kScaled ? a.myz * sc : a.myz);
-    };
+    auto collide_node = [&](const Moments<R> &v) { return collide_stored<S>(v, omega, inv_s_pi); };
+    auto stored_values = [&](const MomentAcc<R> &a, S *v) { stored_moments<S>(a, s_pi, v); };
 
     // Writes the populations leaving the own column to slot h of P (n
     // slots per direction); the own-column ones go to own[3].

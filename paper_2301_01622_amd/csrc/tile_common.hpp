@@ -36,6 +36,43 @@ __device__ __forceinline__ void load_moments(const S *__restrict__ in, int64_t N
     for (int k = 0; k < NF; ++k) m.v[k] = Store<S>::load(in[k * N + idx]);
 }
 
+// Collision of one node from its stored moments (Eqs. 7-8 in moment form);
+// 16-bit storage keeps S * s_pi, undone here.
+template <class S>
+__device__ __forceinline__ Collided<typename Store<S>::real> collide_stored(const Moments<typename Store<S>::real> &v,
+                                                                            typename Store<S>::real omega,
+                                                                            typename Store<S>::real inv_s_pi)
+{
+    using R = typename Store<S>::real;
+    if constexpr (sizeof(S) == 2)
+        return collide<R>(v.v[0], v.v[1], v.v[2], v.v[3], v.v[4] * inv_s_pi, v.v[5] * inv_s_pi, v.v[6] * inv_s_pi,
+                          v.v[7] * inv_s_pi, v.v[8] * inv_s_pi, v.v[9] * inv_s_pi, omega);
+    else
+        return collide<R>(v.v[0], v.v[1], v.v[2], v.v[3], v.v[4], v.v[5], v.v[6], v.v[7], v.v[8], v.v[9], omega);
+}
+
+// The 10 stored values of a finished accumulator (Eqs. 1-3): deviations
+// rho - 1, j and S = P - rho c_s^2 I (times s_pi for 16-bit storage).
+template <class S>
+__device__ __forceinline__ void stored_moments(const MomentAcc<typename Store<S>::real> &a,
+                                               typename Store<S>::real s_pi, S *v)
+{
+    using R = typename Store<S>::real;
+    constexpr bool kScaled = sizeof(S) == 2;
+    const R m3 = R(-1.0 / 3.0);
+    const R sc = kScaled ? s_pi : R(1);
+    v[0] = Store<S>::make(a.r);
+    v[1] = Store<S>::make(a.jx);
+    v[2] = Store<S>::make(a.jy);
+    v[3] = Store<S>::make(a.jz);
+    v[4] = Store<S>::make(kScaled ? fma_(m3, a.r, a.mxx) * sc : fma_(m3, a.r, a.mxx));
+    v[5] = Store<S>::make(kScaled ? fma_(m3, a.r, a.myy) * sc : fma_(m3, a.r, a.myy));
+    v[6] = Store<S>::make(kScaled ? fma_(m3, a.r, a.mzz) * sc : fma_(m3, a.r, a.mzz));
+    v[7] = Store<S>::make(kScaled ? a.mxy * sc : a.mxy);
+    v[8] = Store<S>::make(kScaled ? a.mxz * sc : a.mxz);
+    v[9] = Store<S>::make(kScaled ? a.myz * sc : a.myz);
+}
+
 // Workgroup id -> logical tile id.  Workgroups are handed to the 8 XCDs
 // round-robin (id mod 8); the remap gives each XCD a contiguous range of
 // tiles so that halo re-reads of neighbouring tiles hit the same L2.
