@@ -94,7 +94,6 @@ __global__ __launch_bounds__((kSweepThreads<IX, IY>)) void k_moment_sweep2(const
                                                                         typename Store<S>::real inv_s_pi)
 {
     using R = typename Store<S>::real;
-    constexpr bool kScaled = sizeof(S) == 2;  // 16-bit storage keeps S * s_pi
     constexpr int HX0 = IX + 4, HY0 = IY + 4, N0 = HX0 * HY0;  // R0: sources of the first step
     constexpr int HX1 = IX + 2, HY1 = IY + 2, N1 = HX1 * HY1;  // R1: results of the first step
     constexpr int NI = IX * IY;

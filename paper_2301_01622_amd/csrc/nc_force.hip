@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kNX *kNY) void k_nc_force(const R *__restrict__ phi
     using L = Lattice<Q>;
     const int x = blockIdx.x * kNX + threadIdx.x, y = blockIdx.y * kNY + threadIdx.y, z = blockIdx.z;
     if (x >= nx || y >= ny) return;
-    const int64_t sx = 1, sy = nx, sz = (int64_t)nx * ny;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
     const int64_t n = x + sy * y + sz * z;
     // Offsets of the neighbouring rows, columns and planes (periodic).
     const int64_t ox[3] = {(x == 0 ? nx - 1 : x - 1) - (int64_t)x, 0, (x == nx - 1 ? 0 : x + 1) - (int64_t)x};
