@@ -118,3 +118,17 @@ def test_create_rejects_bad_near_contact_before_device(species, A, hmax):
     rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(8, 8, 8), 19, 0.8, species, ctypes.byref(opts))
     assert rc == _lib.LBM_EINVAL
     assert not ctx.value
+
+
+def test_two_step_sweeps_need_planes_below_2_gib():
+    """A stored xy-plane of 8192 x 8192 FP32 nodes (10 fields, 2.5 GiB) is
+    beyond the sweep's buffer range: asking for two-step sweeps is refused
+    before any device work (the default then runs single steps)."""
+    lib = _lib.load()
+    opts = _lib.Opts()
+    lib.lbm_default_opts(ctypes.byref(opts))
+    opts.steps_per_sweep = 2
+    ctx = ctypes.c_void_p(123)
+    rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(8192, 8192, 3), 19, 0.8, 1, ctypes.byref(opts))
+    assert rc == _lib.LBM_EINVAL
+    assert not ctx.value
