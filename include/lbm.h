@@ -9,14 +9,19 @@
  * non-equilibrium part Eq. 6, ghosts dropped), relaxes them with BGK
  * (Eqs. 7-8), streams them by pulling from the neighbours (Eq. 9) and stores
  * the moments of the streamed set (Eqs. 1-3) in a second copy of the arrays
- * (the flip-flop pair of Sec. III.A).  Two-component fluids follow the
- * colour-gradient model the paper uses (Sec. III.A): one density per species
- * on a shared momentum and pressure tensor, with perturbation and
- * recolouring applied after the collision.
+ * (the flip-flop pair of Sec. III.A).  For one species the library by
+ * default carries each tile of the box through two consecutive steps per
+ * pass over the state (lbm_opts.steps_per_sweep), with the same results as
+ * two single steps.  Two-component fluids follow the colour-gradient model
+ * the paper uses (Sec. III.A): one density per species on a shared momentum
+ * and pressure tensor, with perturbation and recolouring applied after the
+ * collision, optionally with the near-contact force of the LBNCI extension
+ * (Sec. III.C, lbm_opts.nc_A).
  *
  * For comparison the same context can instead run a conventional
- * population-storing BGK scheme (LBM_SCHEME_POPULATION), the "LB with
- * populations" of Sec. IV.
+ * population-storing BGK scheme (LBM_SCHEME_POPULATION, two copies, or
+ * LBM_SCHEME_POPULATION_AA, in place), the "LB with populations" of Sec. IV,
+ * or the moment scheme as the paper's split approach (lbm_opts.split).
  *
  * Conventions shared by every entry point
  *   - Box: nx*ny*nz nodes, fully periodic, node index n = x + nx*(y + ny*z).
