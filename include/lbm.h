@@ -292,6 +292,12 @@ int lbm_costate_from_stored(lbm_ctx *ctx, const void *stored_dev, void *public_d
 /* Number of time steps advanced since creation or the last set_* call. */
 int64_t lbm_steps_done(const lbm_ctx *ctx);
 
+/* Time steps lbm_step carries through each tile per pass over the state for
+ * this context (1 or 2, as resolved from lbm_opts.steps_per_sweep at
+ * creation); 2 also means lbm_step_state2 and lbm_adjoint_step2_stored are
+ * available.  -1 for NULL. */
+int lbm_steps_per_sweep(const lbm_ctx *ctx);
+
 /* Static description of an error code; never NULL. */
 const char *lbm_strerror(int code);
 

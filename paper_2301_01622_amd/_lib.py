@@ -96,6 +96,7 @@ def load() -> ctypes.CDLL:
         "lbm_costate_to_stored": (c_int, [c_void, c_void, c_void]),
         "lbm_costate_from_stored": (c_int, [c_void, c_void, c_void]),
         "lbm_steps_done": (ctypes.c_int64, [c_void]),
+        "lbm_steps_per_sweep": (c_int, [c_void]),
         "lbm_strerror": (ctypes.c_char_p, [c_int]),
         "lbm_last_error": (ctypes.c_char_p, [c_void]),
     }

@@ -553,4 +553,6 @@ int lbm_costate_from_stored(lbm_ctx *c, const void *stored_dev, void *public_dev
 
 int64_t lbm_steps_done(const lbm_ctx *c) { return c ? c->steps : -1; }
 
+int lbm_steps_per_sweep(const lbm_ctx *c) { return c ? c->sweep : -1; }
+
 } // extern "C"

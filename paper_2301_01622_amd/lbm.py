@@ -168,8 +168,7 @@ class LBM:
     def sweeps(self) -> bool:
         """True if the context runs two-step sweeps (and has the two-step
         recompute and adjoint entry points)."""
-        return (self.scheme == "moment" and self.species == 1 and not self.split and self.storage != "f64"
-                and self.steps_per_sweep != 1)
+        return int(self._lib.lbm_steps_per_sweep(self._ctx)) == 2
 
     @property
     def real_dtype(self):

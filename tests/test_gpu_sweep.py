@@ -148,3 +148,16 @@ def test_two_step_entry_points_reject_bad_calls():
     lam = sim.new_costate()
     assert lib.lbm_adjoint_step2_stored(ctx, p(a), p(b), p(lam), p(lam), None) == _lib.LBM_EINVAL
     sim.close()
+
+
+def test_steps_per_sweep_is_reported():
+    from paper_2301_01622_amd.lbm import LBM
+    cases = [(dict(storage="f32"), True), (dict(storage="bf16"), True), (dict(storage="f64"), False),
+             (dict(storage="f32", steps_per_sweep=1), False), (dict(storage="f32", split=True), False)]
+    for kw, expect in cases:
+        sim = LBM((8, 8, 8), 19, 0.8, **kw)
+        assert sim.sweeps == expect, kw
+        sim.close()
+    sim = LBM((8, 8, 8), 19, 0.8, species=2)
+    assert not sim.sweeps
+    sim.close()
