@@ -43,6 +43,54 @@ __global__ __launch_bounds__(kNX *kNY) void k_phi_of_moments(const R *__restrict
     phi[(int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z)] = fma_(R(2) * r1, reciprocal<R>(R(1) + dr), R(-1));
 }
 
+// One step of a probe walk: p in [0, n), |d| <= 1.
+__device__ inline int step_wrap(int p, int d, int n)
+{
+    p += d;
+    return p < 0 ? p + n : (p >= n ? p - n : p);
+}
+
+// Lattice direction c* closest to n = -G/|G|: largest score (c.n)/|c|,
+// exact ties to the smaller |c|^2, then to the lexicographically larger
+// (c_x, c_y, c_z).  Returned as the key 13 + 9 c_x + 3 c_y + c_z, which orders
+// directions as (c_x, c_y, c_z) does.  Only the 7 (D3Q19: 6) candidates
+// whose non-zero components all carry the signs of n are scored: in any
+// other candidate, setting the offending component to zero leaves a rounded
+// sum at least as large with a shorter c, which scores strictly higher
+// whenever the sum is positive; the winner's score is positive (|G_i| > 0
+// on some axis), so no other candidate reaches or ties it.  The sums are
+// formed in the order x, y, z, as the full search over all directions does.
+template <class R>
+__device__ inline void take_better(R score, int key, R &best, int &bkey)
+{
+    if (score > best || (score == best && key > bkey)) {
+        best = score;
+        bkey = key;
+    }
+}
+
+template <int Q, class R>
+__device__ inline int closest_direction(R Gx, R Gy, R Gz)
+{
+    const R ax = Gx < R(0) ? -Gx : Gx, ay = Gy < R(0) ? -Gy : Gy, az = Gz < R(0) ? -Gz : Gz;
+    const int kx = Gx > R(0) ? -9 : 9, ky = Gy > R(0) ? -3 : 3, kz = Gz > R(0) ? -1 : 1;
+    R b1 = ax;
+    int k1 = 13 + kx;
+    take_better(ay, 13 + ky, b1, k1);
+    take_better(az, 13 + kz, b1, k1);
+    const R i2 = R(0.70710678118654752440);
+    R b2 = (ax + ay) * i2;
+    int k2 = 13 + kx + ky;
+    take_better((ax + az) * i2, 13 + kx + kz, b2, k2);
+    take_better((ay + az) * i2, 13 + ky + kz, b2, k2);
+    int key = b2 > b1 ? k2 : k1;
+    if (Q == 27) {
+        const R b3 = ((ax + ay) + az) * R(0.57735026918962576451);
+        if (b3 > (b2 > b1 ? b2 : b1)) key = 13 + kx + ky + kz;
+    }
+    return key;
+}
+
 template <int Q, class R>
 __global__ __launch_bounds__(kNX *kNY) void k_nc_force(const R *__restrict__ phi, R *__restrict__ F, int nx, int ny,
                                                        int nz, int64_t N, R half_Ah, int hmax)
@@ -68,48 +116,27 @@ __global__ __launch_bounds__(kNX *kNY) void k_nc_force(const R *__restrict__ phi
     }
     int found = 0;
     if (Gx != R(0) || Gy != R(0) || Gz != R(0)) {
-        // Direction closest to n = -G/|G|, candidates in the canonical order
-        // (|c|^2 ascending, then c_x, c_y, c_z descending); strict > keeps
-        // the first of equal scores.
-        int bx = 0, by = 0, bz = 0;
-        R best = R(0);
-        bool have = false;
-#pragma unroll
-        for (int s = 1; s <= 3; ++s)
-#pragma unroll
-            for (int cx = 1; cx >= -1; --cx)
-#pragma unroll
-                for (int cy = 1; cy >= -1; --cy)
-#pragma unroll
-                    for (int cz = 1; cz >= -1; --cz) {
-                        if (cx * cx + cy * cy + cz * cz != s || !has_dir<Q>(cx, cy, cz)) continue;
-                        const R inv_len = R(s == 1 ? 1.0 : s == 2 ? 0.70710678118654752440 : 0.57735026918962576451);
-                        const R score = -(R(cx) * Gx + R(cy) * Gy + R(cz) * Gz) * inv_len;
-                        if (!have || score > best) {
-                            have = true;
-                            best = score;
-                            bx = cx;
-                            by = cy;
-                            bz = cz;
-                        }
-                    }
-        // Probes x + k c*, each coordinate stepped with its own wrap.
+        const int key = closest_direction<Q>(Gx, Gy, Gz);
+        const int dx = key / 9 - 1, dy = key / 3 % 3 - 1, dz = key % 3 - 1;
+        // Probes x + k c*, k = 1..h_max, each coordinate stepped with its own
+        // wrap, stopping at the first film; four loads are issued at a time.
         bool seen = phi[n] < R(0);
         int px = x, py = y, pz = z;
-        for (int k = 1; k <= hmax; ++k) {
-            px += bx;
-            py += by;
-            pz += bz;
-            px = px < 0 ? px + nx : (px >= nx ? px - nx : px);
-            py = py < 0 ? py + ny : (py >= ny ? py - ny : py);
-            pz = pz < 0 ? pz + nz : (pz >= nz ? pz - nz : pz);
-            const R f = phi[px + sy * py + sz * pz];
-            if (f < R(0)) {
-                seen = true;
-            } else if (f > R(0) && seen) {
-                found = 1;
-                break;
+        for (int k0 = 1; k0 <= hmax && !found; k0 += 4) {
+            R f[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                px = step_wrap(px, dx, nx);
+                py = step_wrap(py, dy, ny);
+                pz = step_wrap(pz, dz, nz);
+                f[k] = phi[px + sy * py + sz * pz];
             }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k0 + k <= hmax && !found) {
+                    if (f[k] < R(0)) seen = true;
+                    else if (f[k] > R(0) && seen) found = 1;
+                }
         }
     }
     F[n] = found ? half_Ah * Gx : R(0);

@@ -87,3 +87,32 @@ def test_near_contact_rejects_adjoint(LBM):
     p = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
     assert sim._lib.lbm_adjoint_step_stored(sim._ctx, p(st), p(lam), p(lo), None) == _lib.LBM_ESTATE
     sim.close()
+
+
+@pytest.mark.parametrize("hmax", [1, 2, 3, 7])
+@pytest.mark.parametrize("shape", [(20, 21, 70), (3, 4, 5)])
+def test_near_contact_probe_ranges_and_ragged_tiles(LBM, oracle, hmax, shape):
+    """Probe ranges below, at and beyond the staged halo of the force kernel,
+    on a box with ragged tiles in x, y and z (probes that wrap and probes that
+    do not) and on one smaller than a tile (every coordinate wraps, some
+    several times); random phase field, so films are found all over the box."""
+    nz, ny, nx = shape
+    q = 27
+    _say(f"near-contact probes h_max={hmax} {shape} D3Q{q} f64 2 steps")
+    rng = np.random.default_rng(1000 + hmax)
+    r1 = rng.uniform(0.35, 0.65, shape)
+    r2 = 1.0 - r1 + rng.uniform(-0.05, 0.05, shape)
+    u = rng.uniform(-0.02, 0.02, (3,) + shape)
+    H = np.ascontiguousarray(oracle.equilibrium_moments2(r1, r2, u))
+    F, h = oracle.nc_force(2 * r1 / (r1 + r2) - 1, q, AH, hmax)
+    assert (h > 0).sum() > 0
+    A = oracle.sigma_to_A(SIGMA, TAU)
+    ref = oracle.cg_moment_run(H, q, TAU, A, BETA, 2, Ah=AH, hmax=hmax)
+    sim = LBM((nx, ny, nz), q, TAU, species=2, storage="f64", sigma=SIGMA, beta=BETA, nc_A=AH, nc_hmax=hmax)
+    sim.set_moments(torch.from_numpy(H).cuda())
+    sim.step(2)
+    got = sim.get_moments(torch.float64).cpu().numpy()
+    sim.close()
+    err = np.abs(got - ref).max()
+    _say(f"  max err {err:.3e}")
+    assert err <= 1e-12
