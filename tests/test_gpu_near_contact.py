@@ -92,10 +92,10 @@ def test_near_contact_rejects_adjoint(LBM):
 @pytest.mark.parametrize("hmax", [1, 2, 3, 7])
 @pytest.mark.parametrize("shape", [(20, 21, 70), (3, 4, 5)])
 def test_near_contact_probe_ranges_and_ragged_tiles(LBM, oracle, hmax, shape):
-    """Probe ranges below, at and beyond the staged halo of the force kernel,
-    on a box with ragged tiles in x, y and z (probes that wrap and probes that
-    do not) and on one smaller than a tile (every coordinate wraps, some
-    several times); random phase field, so films are found all over the box."""
+    """Probe ranges within one batch of four probe loads and beyond it, on a
+    box with ragged 64 x 4 launch tiles and on one shorter than the probe
+    range (probes wrap, some several times); random phase field, so films
+    are found all over the box."""
     nz, ny, nx = shape
     q = 27
     _say(f"near-contact probes h_max={hmax} {shape} D3Q{q} f64 2 steps")
