@@ -116,3 +116,66 @@ def test_near_contact_probe_ranges_and_ragged_tiles(LBM, oracle, hmax, shape):
     err = np.abs(got - ref).max()
     _say(f"  max err {err:.3e}")
     assert err <= 1e-12
+
+
+def _sampled_nc(oracle, r1, r2, u, q, scheme, nodes, Ah, hmax):
+    """One step of the oracle on the periodic block of radius hmax + 2 around
+    each node: the node's new moments depend on the forces one node away,
+    and those on the phase field up to h_max nodes further."""
+    r = hmax + 2
+    A = oracle.sigma_to_A(SIGMA, TAU)
+    out = []
+    for (z, y, x) in nodes:
+        idx = [np.arange(c - r, c + r + 1) for c in (z, y, x)]
+
+        def cut(a):
+            return np.ascontiguousarray(a.take(idx[0], axis=-3, mode="wrap").take(idx[1], axis=-2, mode="wrap")
+                                        .take(idx[2], axis=-1, mode="wrap"))
+        H = np.ascontiguousarray(oracle.equilibrium_moments2(cut(r1), cut(r2), cut(u)))
+        if scheme == "moment":
+            res = oracle.cg_moment_run(H, q, TAU, A, BETA, 1, Ah=Ah, hmax=hmax)
+        else:
+            f1, f2 = oracle.cg_populations_from_moments(H, q)
+            g1, g2 = oracle.cg_population_run(f1, f2, q, TAU, A, BETA, 1, Ah=Ah, hmax=hmax)
+            res = oracle.cg_moments_from_populations(g1, g2, q)
+        out.append(res[:, r, r, r])
+    return np.array(out)
+
+
+@pytest.mark.parametrize("scheme", ["moment", "population"])
+def test_full_size_near_contact_sampled(LBM, oracle, scheme):
+    """512 x 256 x 256 D3Q19 FP32 with the near-contact force (A_h = 0.01,
+    h_max = 4), in the launch configuration of the benchmark: two drops of
+    radius 40 three nodes apart, one step, nodes in the film between them,
+    on the interfaces, in the drops, in the carrier and at the box corners,
+    node by node against the oracle."""
+    shape = (256, 256, 512)
+    Ah, hmax = 0.01, 4
+    _say(f"512x256x256 near-contact {scheme} scheme sampled, 1 step")
+    c1, c2 = (256 - 1.5 - 40, 128.3, 127.8), (256 + 1.5 + 40, 127.6, 128.1)
+    r1, r2, u = I.droplets(shape, centres=[c1, c2], radius=40.0, velocities=[(0.02, 0, 0), (-0.02, 0, 0)],
+                           width=1.0)
+    sim = LBM((512, 256, 256), 19, TAU, species=2, storage="f32", sigma=SIGMA, beta=BETA, scheme=scheme,
+              nc_A=Ah, nc_hmax=hmax)
+    sim.set_equilibrium(torch.from_numpy(np.stack([r1, r2])).cuda(), torch.from_numpy(u).cuda())
+    sim.step(1)
+    got = sim.get_moments(torch.float64).cpu().numpy()
+    sim.close()
+    rng = np.random.default_rng(11)
+    film = [(128, 128, 256), (128, 128, 255), (128, 128, 257), (130, 126, 256), (125, 131, 254), (128, 136, 256)]
+    film += [(128 + int(rng.integers(-6, 7)), 128 + int(rng.integers(-6, 7)), 256 + int(rng.integers(-3, 4)))
+             for _ in range(8)]
+    nodes = list(film) + [(0, 0, 0), (255, 255, 511), (128, 128, 176), (128, 128, 336)]
+    for _ in range(8):
+        c = [(127.8, 128.3, c1[0]), (128.1, 127.6, c2[0])][rng.integers(2)]
+        d = rng.standard_normal(3)
+        d *= 40.0 / np.linalg.norm(d)
+        nodes.append(tuple(int(round(c[k] + d[k])) % shape[k] for k in range(3)))
+    nodes += [(int(rng.integers(0, 256)), int(rng.integers(0, 256)), int(rng.integers(0, 512))) for _ in range(6)]
+    ref = _sampled_nc(oracle, r1, r2, u, 19, scheme, nodes, Ah, hmax)
+    free = _sampled_nc(oracle, r1, r2, u, 19, scheme, film, 0.0, 0)
+    assert np.abs(ref[:len(film)] - free).max() > 1e-5  # the force acts in the film
+    g = np.array([got[:, z, y, x] for (z, y, x) in nodes])
+    err = np.abs(g - ref).max(axis=0)
+    _say(f"  max err per field {err}")
+    assert err.max() <= 2e-6
