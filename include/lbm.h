@@ -115,8 +115,9 @@ typedef struct {
                         of species 2 is crossed into another drop within nc_hmax nodes along
                         the lattice direction closest to the outward normal, 0 elsewhere
                         (G the colour gradient); added to the mixture collision with Guo's
-                        forcing.  0 (default) = off.  Non-zero needs two species and
-                        1 <= nc_hmax <= 32 (else LBM_EINVAL); the context then holds a
+                        forcing.  0 (default) = off.  Non-zero needs two species,
+                        1 <= nc_hmax <= 32, nz <= 65535 and ny <= 262140 (else
+                        LBM_EINVAL); the context then holds a
                         scratch of 3 N reals (moment scheme 4 N) and the adjoint entry
                         points give LBM_ESTATE */
     int nc_hmax;     /* probe range of the near-contact force, nodes */

@@ -148,8 +148,11 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     if (!(o.s_pi >= 0.0) || !std::isfinite(o.s_pi)) return LBM_EINVAL;
     if (species == 2 && o.scheme == LBM_SCHEME_POPULATION && o.storage != LBM_STORE_F32) return LBM_EINVAL;
 
-    // Near-contact force: two species only, finite strength, 1..32 probes.
-    if (o.nc_A != 0.0 && (species != 2 || !std::isfinite(o.nc_A) || o.nc_hmax < 1 || o.nc_hmax > 32))
+    // Near-contact force: two species only, finite strength, 1..32 probes;
+    // its per-node passes launch one block row per z-plane and 4 rows of y
+    // per block, within the grid's 65535 limit.
+    if (o.nc_A != 0.0 && (species != 2 || !std::isfinite(o.nc_A) || o.nc_hmax < 1 || o.nc_hmax > 32 ||
+                          grid.nz > 65535 || (grid.ny + 3) / 4 > 65535))
         return LBM_EINVAL;
     // Two-step sweeps: one species, fused moment step, not FP64 storage.
     // The sweep addresses one z-plane (at most 2 GiB) per buffer descriptor.

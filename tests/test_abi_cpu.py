@@ -120,6 +120,19 @@ def test_create_rejects_bad_near_contact_before_device(species, A, hmax):
     assert not ctx.value
 
 
+def test_create_rejects_near_contact_beyond_its_launch_grid():
+    """The force passes launch one block row per z-plane: more than 65535
+    planes is refused at creation, not at the first step."""
+    lib = _lib.load()
+    opts = _lib.Opts()
+    lib.lbm_default_opts(ctypes.byref(opts))
+    opts.nc_A, opts.nc_hmax = 0.01, 4
+    ctx = ctypes.c_void_p(123)
+    rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(3, 3, 65536), 19, 0.8, 2, ctypes.byref(opts))
+    assert rc == _lib.LBM_EINVAL
+    assert not ctx.value
+
+
 def test_two_step_sweeps_need_planes_below_2_gib():
     """A stored xy-plane of 8192 x 8192 FP32 nodes (10 fields, 2.5 GiB) is
     beyond the sweep's buffer range: asking for two-step sweeps is refused
