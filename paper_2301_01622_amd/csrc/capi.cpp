@@ -266,6 +266,7 @@ int lbm_set_moments(lbm_ctx *c, const lbm_fields *in)
     const void *dev = nullptr;
     void *owned = nullptr;
     if ((rc = stage_in(c, in, nf, &dev, &owned))) return rc;
+    c->phi_of = nullptr;  // the state changes outside the step
     hipError_t e = lbm::launch_set_moments(c, dev, in->field_stride, in->dtype, c->state[c->cur]);
     if (owned) {
         hipError_t e2 = hipStreamSynchronize(c->stream);
@@ -288,6 +289,7 @@ int lbm_set_equilibrium(lbm_ctx *c, const lbm_fields *prim)
     const void *dev = nullptr;
     void *owned = nullptr;
     if ((rc = stage_in(c, prim, nf, &dev, &owned))) return rc;
+    c->phi_of = nullptr;  // the state changes outside the step
     hipError_t e = lbm::launch_set_equilibrium(c, dev, prim->field_stride, prim->dtype, c->state[c->cur]);
     if (owned) {
         hipError_t e2 = hipStreamSynchronize(c->stream);
@@ -380,8 +382,12 @@ int lbm_step(lbm_ctx *c, int n)
                 if (e == hipSuccess) e = lbm::launch_moment_step(c, in, out, true);
             } else {
                 e = c->scheme == LBM_SCHEME_POPULATION ? lbm::launch_population_step(c, in, out)
-                    : c->species == 2                  ? lbm::launch_cg_step(c, in, out)
+                    : c->species == 2                  ? lbm::launch_cg_step(c, in, out, c->phi_of == in)
                                                        : lbm::launch_moment_step(c, in, out);
+                // The near-contact scratch now holds the phase field of `out`.
+                c->phi_of = e == hipSuccess && c->species == 2 && c->scheme == LBM_SCHEME_MOMENT && c->nc_A != 0.0
+                                ? out
+                                : nullptr;
             }
             if (e == hipSuccess) c->cur = 1 - c->cur;
         }
@@ -439,6 +445,7 @@ int lbm_load_state(lbm_ctx *c, const void *src)
     if (c->scheme == LBM_SCHEME_POPULATION_AA) return fail(c, LBM_ESTATE, "load_state: not for the in-place scheme");
     c->err.clear();
     DeviceGuard g(c->device);
+    c->phi_of = nullptr;  // the state changes outside the step
     hipError_t e = lbm::launch_copy(c, src, c->state[c->cur], (int64_t)c->elem * c->state_elems);
     if (e != hipSuccess) return hip_fail(c, e, "load_state");
     return LBM_OK;
@@ -453,6 +460,7 @@ int lbm_step_state(lbm_ctx *c, const void *src, void *dst)
     c->err.clear();
     DeviceGuard g(c->device);
     hipError_t e = c->species == 2 ? lbm::launch_cg_step(c, src, dst) : lbm::launch_moment_step(c, src, dst);
+    c->phi_of = nullptr;  // the scratch describes dst, not the context's state
     if (e != hipSuccess) return hip_fail(c, e, "step_state");
     return LBM_OK;
 }

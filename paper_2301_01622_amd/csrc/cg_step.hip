@@ -80,10 +80,12 @@ __host__ __device__ constexpr double inv_speed(int cx, int cy, int cz)
 // FORCE: a body force (three arrays of N values, x fastest) enters the
 // mixture collision with Guo's forcing: u* = (j + F/2)/rho in the
 // equilibrium, (1 - omega/2)(u* F + F u*) added to the collided S, j + F
-// streamed.
+// streamed; the phase field phi = 2 rho1/rho - 1 of the stored output is
+// written to phi_out (N values, x fastest) for the next step's force.
 template <int Q, class R, int TX, int TY, bool FORCE>
 __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R *__restrict__ out, TileGrid g,
-                                                    R omega, R A9, R beta, const R *__restrict__ frc)
+                                                    R omega, R A9, R beta, const R *__restrict__ frc,
+                                                    R *__restrict__ phi_out)
 {
     constexpr int NT = TX * TY;
     constexpr int SX = TX + 2, SY = TY + 2, SN = SX * SY;  // source region (radius 1)
@@ -366,6 +368,7 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
             store_out(out + 8 * kBlock + o, a.mxy);
             store_out(out + 9 * kBlock + o, a.mxz);
             store_out(out + 10 * kBlock + o, a.myz);
+            if (FORCE) phi_out[(x0 + lx) + (int64_t)g.nx * ((y0 + ly) + (int64_t)g.ny * d)] = phi_of(a.r, acc[0].rho1);
         }
         acc[0] = acc[1];
         acc[1] = acc[2];
@@ -385,7 +388,7 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
 }
 
 template <int Q, class R, int TX, int TY, int WG_PER_CU>
-hipError_t run(const lbm_ctx *c, const void *in, void *out)
+hipError_t run(const lbm_ctx *c, const void *in, void *out, bool phi_cached)
 {
     TileGrid g;
     g.nx = c->nx;
@@ -400,16 +403,18 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out)
     const int64_t blocks = (int64_t)g.tiles_x * g.tiles_y * g.chunks;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
     if (c->nc_A != 0.0) {
-        // Near-contact force of this state first (into the context's scratch).
-        hipError_t e = launch_nc_force(c, in, nullptr);
+        // Near-contact force of this state first (into the context's scratch:
+        // F, then the phase field, reused when the previous step wrote it).
+        R *phi = static_cast<R *>(c->scratch_nc) + 3 * c->N;
+        hipError_t e = phi_cached ? launch_nc_force(c, nullptr, phi) : launch_nc_force(c, in, nullptr);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, true>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
                            static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega, (R)(c->A / 9.0),
-                           (R)c->beta, static_cast<const R *>(c->scratch_nc));
+                           (R)c->beta, static_cast<const R *>(c->scratch_nc), phi);
     } else {
         hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, false>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
                            static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega, (R)(c->A / 9.0),
-                           (R)c->beta, nullptr);
+                           (R)c->beta, nullptr, nullptr);
     }
     return hipGetLastError();
 }
@@ -427,14 +432,15 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out)
 #define LBM_CG_WG 2
 #endif
 
-hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out)
+hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out, bool phi_cached)
 {
     if (c->species != 2) return hipErrorNotSupported;
     if (c->storage == LBM_STORE_F32)
-        return c->q == 19 ? run<19, float, LBM_CG_TX, LBM_CG_TY, LBM_CG_WG>(c, in, out)
-                          : run<27, float, 32, 8, 2>(c, in, out);
+        return c->q == 19 ? run<19, float, LBM_CG_TX, LBM_CG_TY, LBM_CG_WG>(c, in, out, phi_cached)
+                          : run<27, float, 32, 8, 2>(c, in, out, phi_cached);
     if (c->storage == LBM_STORE_F64)
-        return c->q == 19 ? run<19, double, 32, 4, 2>(c, in, out) : run<27, double, 32, 4, 2>(c, in, out);
+        return c->q == 19 ? run<19, double, 32, 4, 2>(c, in, out, phi_cached)
+                          : run<27, double, 32, 4, 2>(c, in, out, phi_cached);
     return hipErrorInvalidValue;
 }
 

@@ -22,6 +22,7 @@ struct lbm_ctx {
     double nc_A = 0.0;  // near-contact force strength (two species; 0 = off)
     int nc_hmax = 0;    // near-contact probe range (nodes)
     void *scratch_nc = nullptr;  // near-contact force (3 N reals), then the moment scheme's phase field (N)
+    const void *phi_of = nullptr;  // state whose phase field that scratch holds (moment scheme), or none
     int nfields = 0;  // stored arrays per state copy
     size_t elem = 4;  // bytes per stored element
     int64_t state_elems = 0;  // elements per state copy (blocked moment layout or q x N populations)
@@ -60,7 +61,10 @@ hipError_t launch_adjoint_sweep2(const lbm_ctx *c, const void *state_t1, const v
                                  void *lam_out, double *dtau_accum);
 
 // Moment scheme, two species (colour gradient).
-hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out);
+// Two-component moment step.  With the near-contact force the step also
+// writes the phase field of its output into the scratch after the force;
+// phi_cached says that the scratch already holds the phase field of `in`.
+hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out, bool phi_cached = false);
 
 // Discrete adjoint of the one-species moment step; co-states in the public
 // layout, or in the stored (blocked) layout of the state if `stored`.
