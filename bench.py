@@ -234,7 +234,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU halo exchange is a design, not part of this build)", file=sys.stderr)
+              "(the library runs on one GPU; a multi-GPU halo exchange is not implemented)", file=sys.stderr)
         return 2
 
     import torch
