@@ -16,11 +16,11 @@
  * the paper uses (Sec. III.A): one density per species on a shared momentum
  * and pressure tensor, with perturbation and recolouring applied after the
  * collision, optionally with the near-contact force of the LBNCI extension
- * (Sec. III.C, lbm_opts.nc_A).
+ * (Sec. III.B, lbm_opts.nc_A).
  *
  * For comparison the same context can instead run a conventional
  * population-storing BGK scheme (LBM_SCHEME_POPULATION, two copies, or
- * LBM_SCHEME_POPULATION_AA, in place), the "LB with populations" of Sec. IV,
+ * LBM_SCHEME_POPULATION_AA, in place), the "LB with populations" of Sec. IV.A,
  * or the moment scheme as the paper's split approach (lbm_opts.split).
  *
  * Conventions shared by every entry point
@@ -92,12 +92,14 @@ typedef struct {
     int storage;     /* LBM_STORE_*; default LBM_STORE_F32 (population scheme: F32 or F64) */
     double beta;     /* recolouring strength, two species; default 0.7 */
     double sigma;    /* surface tension, two species; default 0.01 (A = 9 sigma / (2 tau)) */
-    double s_pi;     /* scale of the stored S; 0 = default (1024 for F16, 1 otherwise) */
+    double s_pi;     /* scale of the stored S; 0 = default (1024 for F16, 1 otherwise).  A
+                        power of two for one species with F16/BF16 moment storage; 0 or 1
+                        for every other context (else LBM_EINVAL) */
     void *stream;    /* hipStream_t to run on; NULL = the null stream */
     int device;      /* HIP device ordinal; -1 = current device */
     int check_every; /* lbm_step runs the FP64 check every this many steps; 0 = never */
     int split;       /* 0 (default): fused step, one kernel.  1: the paper's split approach
-                        (Sec. III), for comparison: a collision pass relaxes the stored moments
+                        (Sec. III.A), for comparison: a collision pass relaxes the stored moments
                         in place (rho, j, S) -> (rho, j, S'), then the streaming pass
                         reconstructs, pulls and sums.  Moment scheme, one species only
                         (else LBM_EINVAL); results equal the fused step's bit for bit with
@@ -110,7 +112,7 @@ typedef struct {
                         storage and one stored xy-plane below 2 GiB (else LBM_EINVAL).  0 (default): 2 where available, else 1.
                         lbm_step falls back to single steps for an odd remainder and where
                         a check_every health check falls between the two steps */
-    double nc_A;     /* near-contact force of the LBNCI extension (Sec. III.C), two species:
+    double nc_A;     /* near-contact force of the LBNCI extension (Sec. III.B), two species:
                         F = -A_h n delta_I, read as F = (nc_A/2) G at nodes from which a film
                         of species 2 is crossed into another drop within nc_hmax nodes along
                         the lattice direction closest to the outward normal, 0 elsewhere

@@ -10,12 +10,13 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["lattice.c", "moment_lb.c", "population_lb.c", "color_gradient.c", "adjoint.c", "adjoint_cg.c"]
 LIB = os.path.join(HERE, "liboracle.so")
+COMPILER = "gcc"
+FLAGS = ["-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra"]
 
 
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-o", LIB + ".tmp", *srcs, "-lm"]
+    cmd = [COMPILER, *FLAGS, "-o", LIB + ".tmp", *srcs, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -30,7 +30,7 @@
  *   one relaxation time for the mixture (viscosity ratio one, Sec. IV)
  *
  *
- * Near-contact force (the LBNCI extension, Sec. III.C), optional: the paper
+ * Near-contact force (the LBNCI extension, Sec. III.B), optional: the paper
  * gives F_rep = -A_h[h(x)] n delta_I with delta_I proportional to grad phi,
  * but neither how h(x) is found nor the form of A_h nor how the force enters
  * the scheme.  Readings:

@@ -146,6 +146,15 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     if (species == 2 && o.storage != LBM_STORE_F32 && o.storage != LBM_STORE_F64) return LBM_EINVAL;
     if (species == 2 && (!(o.beta >= 0.0) || !(o.sigma >= 0.0))) return LBM_EINVAL;
     if (!(o.s_pi >= 0.0) || !std::isfinite(o.s_pi)) return LBM_EINVAL;
+    // The scale of the stored S is applied only where S is stored in 16 bits
+    // (one species, moment scheme); elsewhere it must stay 1.  A power of two
+    // keeps the scaling exact.
+    if (o.s_pi != 0.0) {
+        const bool scaled = o.scheme == LBM_SCHEME_MOMENT && species == 1 &&
+                            (o.storage == LBM_STORE_F16 || o.storage == LBM_STORE_BF16);
+        int e2 = 0;
+        if (scaled ? std::frexp(o.s_pi, &e2) != 0.5 : o.s_pi != 1.0) return LBM_EINVAL;
+    }
     if (species == 2 && o.scheme == LBM_SCHEME_POPULATION && o.storage != LBM_STORE_F32) return LBM_EINVAL;
 
     // Near-contact force: two species only, finite strength, 1..32 probes;

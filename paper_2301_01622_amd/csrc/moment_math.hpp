@@ -80,7 +80,7 @@ __device__ __forceinline__ Collided<R> collide(R dr, R jx, R jy, R jz, R sxx, R 
 }
 
 // The same record built from moments that are already post-collision (the
-// split approach of Sec. III stores them between its two passes); equal to
+// split approach of Sec. III.A stores them between its two passes); equal to
 // collide() applied to the pre-collision moments when S' was stored exactly.
 template <class R>
 __device__ __forceinline__ Collided<R> collided_from(R dr, R jx, R jy, R jz, R sxx, R syy, R szz, R sxy, R sxz,

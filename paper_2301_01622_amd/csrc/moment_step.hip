@@ -23,7 +23,7 @@
 // workgroups an XCD receives (consecutive ids modulo 8) cover a contiguous
 // block of tiles, keeping halo re-reads inside one L2.
 //
-// The paper's split approach (Sec. III) is available for comparison: a
+// The paper's split approach (Sec. III.A) is available for comparison: a
 // node-local collision pass relaxes the stored moments in place, and the
 // tile kernel, instantiated with COLLIDED, then only reconstructs, pulls and
 // sums.  It moves 36 stored values per node instead of 20.

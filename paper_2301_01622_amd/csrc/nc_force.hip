@@ -1,4 +1,4 @@
-// Near-contact force of the LBNCI extension (Sec. III.C) for the
+// Near-contact force of the LBNCI extension (Sec. III.B) for the
 // two-component schemes.
 //
 // The paper gives F_rep = -A_h[h(x)] n delta_I, with h(x) the distance

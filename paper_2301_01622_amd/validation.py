@@ -1,4 +1,4 @@
-"""The paper's validation experiment on the GPU (Sec. V): two drops of
+"""The paper's validation experiment on the GPU (Sec. IV): two drops of
 diameter 30 in a periodic 128^3 box, viscosity ratio one, run side by side
 with the moment scheme (this library's step) and the colour-gradient LB with
 stored populations (the same-GPU baseline), comparing

@@ -145,3 +145,28 @@ def test_two_step_sweeps_need_planes_below_2_gib():
     rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(8192, 8192, 3), 19, 0.8, 1, ctypes.byref(opts))
     assert rc == _lib.LBM_EINVAL
     assert not ctx.value
+
+
+@pytest.mark.parametrize("species,scheme,storage,s_pi", [
+    (1, 0, 1, 2.0),      # FP32 storage keeps S unscaled: only 0 or 1
+    (1, 0, 0, 1024.0),   # FP64 likewise
+    (2, 0, 1, 4.0),      # two species likewise
+    (1, 1, 1, 8.0),      # population scheme: no stored S
+    (1, 0, 2, 1000.0),   # 16-bit storage: a power of two only
+    (1, 0, 3, 0.75),
+    (1, 0, 2, -1.0),
+    (1, 0, 2, float("inf")),
+])
+def test_create_rejects_s_pi_where_not_applied(species, scheme, storage, s_pi):
+    """The scale of the stored S is applied by the kernels only for one
+    species with 16-bit moment storage; any other value elsewhere would be
+    silently read as unscaled, so creation refuses it before device work."""
+    lib = _lib.load()
+    opts = _lib.Opts()
+    lib.lbm_default_opts(ctypes.byref(opts))
+    assert opts.s_pi == 0.0
+    opts.scheme, opts.storage, opts.s_pi = scheme, storage, s_pi
+    ctx = ctypes.c_void_p(123)
+    rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(8, 8, 8), 19, 0.8, species, ctypes.byref(opts))
+    assert rc == _lib.LBM_EINVAL
+    assert not ctx.value

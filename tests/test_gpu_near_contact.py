@@ -1,4 +1,4 @@
-"""GPU parity of the near-contact force (the LBNCI term of Sec. III.C, under
+"""GPU parity of the near-contact force (the LBNCI term of Sec. III.B, under
 the readings stated in csrc/nc_force.hip and the oracle) for both
 two-component schemes, against the FP64 oracle: two drops whose interfaces
 are a few nodes apart, so that films are found by the probes."""

@@ -1,4 +1,4 @@
-"""The paper's split approach (Sec. III): a collision pass stores the
+"""The paper's split approach (Sec. III.A): a collision pass stores the
 post-collision moments, a streaming pass reconstructs, pulls and sums.  The
 split is a different schedule of the same arithmetic, so with FP32/FP64
 storage (S' stored exactly in the precision it is computed in) it must equal

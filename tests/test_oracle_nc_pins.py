@@ -1,4 +1,4 @@
-"""Pins of the oracle's near-contact force (the LBNCI term of Sec. III.C,
+"""Pins of the oracle's near-contact force (the LBNCI term of Sec. III.B,
 under the readings stated in oracle/color_gradient.c) and of its Guo forcing.
 
 * Two flat slabs of species 1 with sharp interfaces across a film of w nodes:
