@@ -123,6 +123,14 @@ typedef struct {
                         scratch of 3 N reals (moment scheme 4 N) and the adjoint entry
                         points give LBM_ESTATE */
     int nc_hmax;     /* probe range of the near-contact force, nodes */
+    void *state_buffers[2]; /* optional caller-owned device buffers for the two state copies
+                        (flip-flop pair; the in-place population scheme uses only [0]), e.g.
+                        allocated by the caller's framework.  NULL (default): the library
+                        allocates them.  Each must hold state_buffer_bytes >=
+                        lbm_state_bytes_for() bytes on the context's device and stay valid
+                        until lbm_destroy; the library overwrites them (the fluid starts at
+                        rest) and never frees them.  Both NULL or both set (LBM_EINVAL) */
+    int64_t state_buffer_bytes; /* size of each buffer in state_buffers */
 } lbm_opts;
 
 /* Caller-owned moment buffers, see the layout above. */
@@ -171,6 +179,36 @@ int lbm_set_moments(lbm_ctx *ctx, const lbm_fields *in);
  * destination is host memory.  Errors: LBM_EINVAL, LBM_EDEVICE. */
 int lbm_get_moments(const lbm_ctx *ctx, lbm_fields *out);
 
+/* The equilibrium moments of primitive fields, written to a caller buffer
+ * (the context's state is not touched): the map from an initial density and
+ * velocity field to an initial state with zero non-equilibrium part,
+ * rho^k, j = rho u, P = rho c_s^2 I + rho u u (the moments of the
+ * equilibrium populations of Eq. 5).
+ *   primitive : rho (one species) or rho1, rho2 (two species), then ux, uy,
+ *               uz; lbm_fields layout, F32 or F64, host or device
+ *   moments   : receives the public moment fields (10 or 11), F32 or F64,
+ *               host or device
+ * Arithmetic in FP64, one rounding at the store.  Asynchronous for device
+ * buffers; with a host buffer the call synchronises the stream.
+ * Errors: LBM_EINVAL (NULL, bad dtype or stride), LBM_ENOMEM, LBM_EDEVICE. */
+int lbm_equilibrium_moments(lbm_ctx *ctx, const lbm_fields *primitive, lbm_fields *moments);
+
+/* Transpose of the Jacobian of lbm_equilibrium_moments at `primitive`,
+ * applied to a gradient with respect to the moments: the chain from dL/dM(0)
+ * to dL/drho^k and dL/du of the initial fields.  With g_j and g_P the
+ * gradients of j and of the six stored P components (an off-diagonal stored
+ * component counts once),
+ *   dL/drho^k = g_rho^k + u.g_j + sum_ab g_P_ab (u_a u_b + delta_ab c_s^2),
+ *   dL/du_c   = rho g_j_c + rho sum_ab g_P_ab (delta_ac u_b + u_a delta_bc).
+ *   primitive      : as for lbm_equilibrium_moments
+ *   grad_moments   : public moment layout (10 or 11 fields)
+ *   grad_primitive : receives species + 3 fields in the primitive layout
+ * F32 or F64, host or device each; FP64 arithmetic.  Asynchronous for device
+ * buffers; with a host buffer the call synchronises the stream.
+ * Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE. */
+int lbm_equilibrium_moments_adjoint(lbm_ctx *ctx, const lbm_fields *primitive, const lbm_fields *grad_moments,
+                                    lbm_fields *grad_primitive);
+
 /* Sets an equilibrium state from primitive fields: the buffer holds
  * rho (one species) or rho1, rho2 (two species) followed by ux, uy, uz; the
  * moments become rho^k, j = rho u and P = rho c_s^2 I + rho u u (the second
@@ -198,6 +236,12 @@ int lbm_reduce(lbm_ctx *ctx, double out[5]);
  * (every stored value of every node read once and written once).  Either
  * pointer may be NULL. */
 int lbm_memory_info(const lbm_ctx *ctx, int64_t *state_bytes, int64_t *step_bytes);
+
+/* Bytes of one state copy that lbm_create(grid, lattice, tau, species, opts)
+ * would use (the size each of lbm_opts.state_buffers must have), without
+ * creating a context.  Errors: LBM_EINVAL (NULL bytes, or a setup
+ * lbm_create refuses). */
+int lbm_state_bytes_for(lbm_grid grid, int lattice, int species, const lbm_opts *opts, int64_t *bytes);
 
 /* Size in bytes of one time level of the stored state (the buffer that
  * lbm_save_state fills).  The moment scheme stores its fields in an internal
@@ -236,34 +280,47 @@ int lbm_step_state2(lbm_ctx *ctx, const void *src_state, void *mid_state, void *
  * transpose of the Jacobian of one step (one species: Eqs. 4-9 and 1-3; two
  * species: the colour-gradient step of Sec. III.A with the perturbation and
  * recolouring operators of Sec. III.B, smoothed normal, A held at 9 sigma/(2 tau)).
- *   state_t    : device, the state M(t) the forward step started from, in the
- *                format of lbm_save_state
- *   lam_next   : device, co-state of M(t+1) in the public layout: one species
- *                10 fields of N values (rho, j, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz),
- *                two species 11 fields (rho1, rho2, j, P as before); FP64 for
- *                LBM_STORE_F64 contexts, FP32 otherwise
- *   lam_out    : device, receives the co-state of M(t), same layout; must not
- *                overlap lam_next
- *   dtau_accum : device pointer to one double or NULL; the step adds its
- *                contribution to dL/dtau (sum over nodes, FP64, fixed order;
- *                two species: at fixed sigma, so A varies with tau)
- * A stored off-diagonal P component stands for P_ab and P_ba together, so
- * its co-state is the derivative with respect to that one stored value.
- * Two species: FP32 or FP64 storage only; the first call allocates a device
- * buffer of 3 N reals for the co-state of the colour gradient, which the
- * context keeps (LBM_ENOMEM if that fails).  Asynchronous.
- * Errors: LBM_EINVAL (NULL or aliased), LBM_ESTATE (population scheme, or two
- * species with FP16/BF16 storage), LBM_ENOMEM, LBM_EDEVICE. */
-int lbm_adjoint_step(lbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out, double *dtau_accum);
+ *   state_t    : the state M(t) the forward step starts from, public moment
+ *                layout (10 or 11 fields); it is first converted to the
+ *                storage format exactly as lbm_set_moments would store it,
+ *                and the step is linearised at that stored state
+ *   lam_next   : co-state of M(t+1), public moment layout
+ *   lam_out    : receives the co-state of M(t), public moment layout; must
+ *                not be the same buffer as lam_next
+ *   dtau_accum : host pointer to one double, or NULL; the step's dL/dtau
+ *                (sum over nodes in FP64, fixed order; two species: at fixed
+ *                sigma, so A varies with tau) is added to it
+ * Each buffer may be host or device memory, F32 or F64; the kernels compute
+ * in FP64 for LBM_STORE_F64 contexts and FP32 otherwise, and co-states are
+ * converted to that type on the way in and rounded to the caller's type on
+ * the way out.  A stored off-diagonal P component stands for P_ab and P_ba
+ * together, so its co-state is the derivative with respect to that one
+ * stored value.  The context's own state is not touched.  The first call
+ * allocates a work area the context keeps (one stored state, two stored
+ * co-states; two species also a buffer of 3 N reals for the co-state of the
+ * colour gradient).  The call synchronises the stream when dtau_accum is
+ * non-NULL or a buffer is in host memory.  Two species: FP32 or FP64 storage
+ * only.  A checkpointed rollout instead keeps its states in the stored
+ * format and its co-states in the stored layout (lbm_adjoint_step_stored).
+ * Errors: LBM_EINVAL (NULL, bad dtype or stride, lam_out == lam_next),
+ * LBM_ESTATE (population scheme, near-contact force, or two species with
+ * FP16/BF16 storage), LBM_ENOMEM, LBM_EDEVICE. */
+int lbm_adjoint_step(lbm_ctx *ctx, const lbm_fields *state_t, const lbm_fields *lam_next, lbm_fields *lam_out,
+                     double *dtau_accum);
 
-/* The same reverse step with both co-states in the stored (blocked) layout
- * of the state instead of the public one: lam_next and lam_out are device
- * buffers of lbm_costate_bytes() bytes (real type as for lbm_adjoint_step).
- * A checkpointed rollout keeps its co-state in this layout between steps and
- * converts it only at the ends (lbm_costate_to_stored / _from_stored); the
- * results equal those of lbm_adjoint_step bit for bit.  Slots of the layout
- * that belong to no node are neither read nor written.  Errors as for
- * lbm_adjoint_step. */
+/* The same reverse step on the library's own formats, for checkpointed
+ * rollouts: state_t is a device buffer in the format of lbm_save_state;
+ * lam_next and lam_out are device buffers of lbm_costate_bytes() bytes in the
+ * stored (blocked) layout of the state, with the kernels' real type (FP64 for
+ * LBM_STORE_F64, else FP32); dtau_accum is a device pointer to one double or
+ * NULL, added to on the stream.  A rollout keeps its co-state in this layout
+ * between steps and converts it only at the ends (lbm_costate_to_stored /
+ * _from_stored); the results equal those of lbm_adjoint_step from the same
+ * stored state bit for bit.  Slots of the layout that belong to no node are
+ * neither read nor written.  Asynchronous; the two-species co-state buffer
+ * is allocated on the first call as for lbm_adjoint_step.
+ * Errors: LBM_EINVAL (NULL, or lam_next == lam_out), LBM_ESTATE, LBM_ENOMEM,
+ * LBM_EDEVICE. */
 int lbm_adjoint_step_stored(lbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out,
                             double *dtau_accum);
 

@@ -130,6 +130,47 @@ def equilibrium_moments2(rho1, rho2, u) -> np.ndarray:
     return np.ascontiguousarray(np.concatenate([rho1[None], rho2[None], H1[1:]], axis=0))
 
 
+def equilibrium_adjoint(rho_k, u, gM) -> np.ndarray:
+    """Chain rule through the equilibrium map: given dL/dM of a state built by
+    equilibrium_moments (one species, rho_k of shape (nz, ny, nx)) or
+    equilibrium_moments2 (rho_k = (rho1, rho2)), returns dL/d(rho_k, u) with
+    shape (species + 3, nz, ny, nx).  The map is M = (rho^k, rho u,
+    rho c_s^2 I + rho u u); written term by term: rho enters j_a = rho u_a
+    and P_ab = rho u_a u_b + rho c_s^2 delta_ab, and u_c enters j_c and every
+    P_ab with a = c or b = c."""
+    u = np.asarray(u, dtype=np.float64)
+    gM = np.asarray(gM, dtype=np.float64)
+    rho_k = np.asarray(rho_k, dtype=np.float64)
+    species = 1 if rho_k.ndim == 3 else rho_k.shape[0]
+    rho = rho_k if species == 1 else rho_k.sum(0)
+    off = 1 if species == 1 else 2
+    gj = gM[off:off + 3]
+    gP = gM[off + 3:off + 9]
+    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    # d/drho of j and P at fixed u
+    g_rho = np.zeros_like(rho)
+    for a in range(3):
+        g_rho += gj[a] * u[a]
+    for k, (a, b) in enumerate(pairs):
+        g_rho += gP[k] * (u[a] * u[b] + (CS2 if a == b else 0.0))
+    # d/du_c of j and P at fixed rho
+    g_u = np.zeros_like(u)
+    for c in range(3):
+        g_u[c] += rho * gj[c]
+    for k, (a, b) in enumerate(pairs):
+        # d(rho u_a u_b)/du_a = rho u_b and d/du_b = rho u_a (both when a = b)
+        g_u[a] += gP[k] * rho * u[b]
+        g_u[b] += gP[k] * rho * u[a]
+    out = np.empty((species + 3,) + rho.shape)
+    if species == 1:
+        out[0] = gM[0] + g_rho
+    else:
+        out[0] = gM[0] + g_rho
+        out[1] = gM[1] + g_rho
+    out[species:] = g_u
+    return out
+
+
 def sigma_to_A(sigma: float, tau: float) -> float:
     """Perturbation amplitude for a surface tension sigma (sigma = 2 A tau / 9)."""
     return 9.0 * sigma / (2.0 * tau)

@@ -42,6 +42,8 @@ class Opts(ctypes.Structure):
         ("steps_per_sweep", ctypes.c_int),
         ("nc_A", ctypes.c_double),
         ("nc_hmax", ctypes.c_int),
+        ("state_buffers", ctypes.c_void_p * 2),
+        ("state_buffer_bytes", ctypes.c_int64),
     ]
 
 
@@ -90,7 +92,10 @@ def load() -> ctypes.CDLL:
         "lbm_step_state": (c_int, [c_void, c_void, c_void]),
         "lbm_step_state2": (c_int, [c_void, c_void, c_void, c_void]),
         "lbm_adjoint_step2_stored": (c_int, [c_void, c_void, c_void, c_void, c_void, c_void]),
-        "lbm_adjoint_step": (c_int, [c_void, c_void, c_void, c_void, c_void]),
+        "lbm_adjoint_step": (c_int, [c_void, P(Fields), P(Fields), P(Fields), P(c_dbl)]),
+        "lbm_equilibrium_moments": (c_int, [c_void, P(Fields), P(Fields)]),
+        "lbm_equilibrium_moments_adjoint": (c_int, [c_void, P(Fields), P(Fields), P(Fields)]),
+        "lbm_state_bytes_for": (c_int, [Grid, c_int, c_int, P(Opts), P(ctypes.c_int64)]),
         "lbm_adjoint_step_stored": (c_int, [c_void, c_void, c_void, c_void, c_void]),
         "lbm_costate_bytes": (c_int, [c_void, P(ctypes.c_int64)]),
         "lbm_costate_to_stored": (c_int, [c_void, c_void, c_void]),

@@ -86,6 +86,64 @@ int stage_in(const lbm_ctx *c, const lbm_fields *f, int nfields, const void **de
 
 int public_fields(const lbm_ctx *c) { return c->species == 1 ? 10 : 11; }
 
+size_t dtype_bytes(int dtype) { return dtype == LBM_DTYPE_F64 ? 8 : 4; }
+
+// Device view of a caller output buffer: the buffer itself when it is device
+// memory, else a fresh device buffer of the same layout (*owned) that
+// finish_out copies to the host buffer.
+int stage_out(const lbm_ctx *c, const lbm_fields *f, int nfields, void **dev, void **owned)
+{
+    *owned = nullptr;
+    if (f->on_device) {
+        *dev = f->base;
+        return LBM_OK;
+    }
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, dtype_bytes(f->dtype) * (size_t)f->field_stride * (size_t)nfields);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMalloc(staging)");
+    *dev = d;
+    *owned = d;
+    return LBM_OK;
+}
+
+// Completes a staged output (copy to the host, synchronise) and frees the
+// staging buffers; e is the status of the launches so far.
+hipError_t finish_io(const lbm_ctx *c, hipError_t e, const lbm_fields *out, int nfields, void *out_owned,
+                     void *in_owned_a, void *in_owned_b = nullptr)
+{
+    if (e == hipSuccess && out_owned)
+        e = hipMemcpyAsync(out->base, out_owned, dtype_bytes(out->dtype) * (size_t)out->field_stride * (size_t)nfields,
+                           hipMemcpyDeviceToHost, c->stream);
+    if (out_owned || in_owned_a || in_owned_b) {
+        hipError_t e2 = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess) e = e2;
+    }
+    if (out_owned) (void)hipFree(out_owned);
+    if (in_owned_a) (void)hipFree(in_owned_a);
+    if (in_owned_b) (void)hipFree(in_owned_b);
+    return e;
+}
+
+// Stored arrays per state copy, bytes per stored element and elements per
+// copy (blocked moment layout, or q x N populations) for a validated setup.
+struct StatePlan {
+    int nfields;
+    size_t elem;
+    int64_t elems;
+    int copies;
+};
+
+StatePlan state_plan(lbm_grid g, int lattice, int species, const lbm_opts &o)
+{
+    StatePlan p;
+    p.nfields = o.scheme == LBM_SCHEME_MOMENT ? (species == 1 ? 10 : 11) : lattice * species;
+    p.elem = storage_bytes(o.storage);
+    p.elems = o.scheme == LBM_SCHEME_MOMENT ? lbm::moment_layout(g.nx, g.ny, p.nfields).plane * g.nz
+                                            : (int64_t)p.nfields * g.nx * g.ny * g.nz;
+    p.copies = o.scheme == LBM_SCHEME_POPULATION_AA ? 1 : 2;
+    return p;
+}
+
 } // namespace
 
 extern "C" {
@@ -105,6 +163,9 @@ void lbm_default_opts(lbm_opts *o)
     o->steps_per_sweep = 0;
     o->nc_A = 0.0;
     o->nc_hmax = 0;
+    o->state_buffers[0] = nullptr;
+    o->state_buffers[1] = nullptr;
+    o->state_buffer_bytes = 0;
 }
 
 const char *lbm_strerror(int code)
@@ -122,16 +183,12 @@ const char *lbm_strerror(int code)
 
 const char *lbm_last_error(const lbm_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
 
-int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int species, const lbm_opts *opts)
+// Validates a setup (every rule of lbm_create except tau and the external
+// state buffers); *sweep receives the resolved steps per sweep.
+static int validate(lbm_grid grid, int lattice, int species, const lbm_opts &o, int *sweep)
 {
-    if (!out) return LBM_EINVAL;
-    *out = nullptr;
-    lbm_opts o;
-    lbm_default_opts(&o);
-    if (opts) o = *opts;
     if (grid.nx < 3 || grid.ny < 3 || grid.nz < 3) return LBM_EINVAL;
     if (lattice != 19 && lattice != 27) return LBM_EINVAL;
-    if (!(tau > 0.5) || !std::isfinite(tau)) return LBM_EINVAL;
     if (species != 1 && species != 2) return LBM_EINVAL;
     if (o.scheme != LBM_SCHEME_MOMENT && o.scheme != LBM_SCHEME_POPULATION && o.scheme != LBM_SCHEME_POPULATION_AA)
         return LBM_EINVAL;
@@ -170,7 +227,29 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
                            lbm::moment_layout(grid.nx, grid.ny, 10).plane * (int64_t)storage_bytes(o.storage) <
                                ((int64_t)1 << 31);
     if (o.steps_per_sweep < 0 || o.steps_per_sweep > 2 || (o.steps_per_sweep == 2 && !sweep2_ok)) return LBM_EINVAL;
-    const int sweep = o.steps_per_sweep == 0 ? (sweep2_ok ? 2 : 1) : o.steps_per_sweep;
+    *sweep = o.steps_per_sweep == 0 ? (sweep2_ok ? 2 : 1) : o.steps_per_sweep;
+    return LBM_OK;
+}
+
+int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int species, const lbm_opts *opts)
+{
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    lbm_opts o;
+    lbm_default_opts(&o);
+    if (opts) o = *opts;
+    if (!(tau > 0.5) || !std::isfinite(tau)) return LBM_EINVAL;
+    int sweep = 1;
+    if (validate(grid, lattice, species, o, &sweep) != LBM_OK) return LBM_EINVAL;
+    const StatePlan plan = state_plan(grid, lattice, species, o);
+    // Caller-owned state copies: both given (one for the in-place scheme),
+    // each large enough, or none.
+    const bool external = o.state_buffers[0] || o.state_buffers[1];
+    if (external) {
+        const bool pair_ok = plan.copies == 1 || (o.state_buffers[1] && o.state_buffers[1] != o.state_buffers[0]);
+        if (!o.state_buffers[0] || !pair_ok || o.state_buffer_bytes < (int64_t)plan.elem * plan.elems)
+            return LBM_EINVAL;
+    }
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
     if (!c) return LBM_ENOMEM;
     c->nx = grid.nx;
@@ -193,11 +272,11 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     c->sweep = sweep;
     c->nc_A = o.nc_A;
     c->nc_hmax = o.nc_A != 0.0 ? o.nc_hmax : 0;
-    c->elem = storage_bytes(o.storage);
-    c->nfields = o.scheme == LBM_SCHEME_MOMENT ? (species == 1 ? 10 : 11) : lattice * species;
+    c->elem = plan.elem;
+    c->nfields = plan.nfields;
     c->lay = lbm::moment_layout(c->nx, c->ny, c->nfields);
     c->lay3 = lbm::moment_layout(c->nx, c->ny, 3);
-    c->state_elems = o.scheme == LBM_SCHEME_MOMENT ? c->lay.plane * c->nz : (int64_t)c->nfields * c->N;
+    c->state_elems = plan.elems;
 
     if (o.device >= 0) {
         c->device = o.device;
@@ -207,8 +286,13 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
     }
     DeviceGuard g(c->device);
     const size_t bytes = c->elem * (size_t)c->state_elems;
-    const int copies = c->scheme == LBM_SCHEME_POPULATION_AA ? 1 : 2;  // in place: one copy
+    const int copies = plan.copies;  // in place: one copy
+    c->owns_state = !external;
     for (int k = 0; k < copies; ++k) {
+        if (external) {
+            c->state[k] = o.state_buffers[k];
+            continue;
+        }
         hipError_t e = hipMalloc(&c->state[k], bytes);
         if (e != hipSuccess) {
             lbm_destroy(c);
@@ -254,7 +338,9 @@ int lbm_destroy(lbm_ctx *c)
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (int k = 0; k < 2; ++k)
-        if (c->state[k]) (void)hipFree(c->state[k]);
+        if (c->state[k] && c->owns_state) (void)hipFree(c->state[k]);
+    if (c->adj_work) (void)hipFree(c->adj_work);
+    if (c->adj_dtau) (void)hipFree(c->adj_dtau);
     if (c->partials) (void)hipFree(c->partials);
     if (c->red_out) (void)hipFree(c->red_out);
     if (c->scratch_phi) (void)hipFree(c->scratch_phi);
@@ -435,6 +521,70 @@ int lbm_state_bytes(const lbm_ctx *c, int64_t *bytes)
     return LBM_OK;
 }
 
+int lbm_state_bytes_for(lbm_grid grid, int lattice, int species, const lbm_opts *opts, int64_t *bytes)
+{
+    if (!bytes) return LBM_EINVAL;
+    lbm_opts o;
+    lbm_default_opts(&o);
+    if (opts) o = *opts;
+    int sweep = 1;
+    if (validate(grid, lattice, species, o, &sweep) != LBM_OK) return LBM_EINVAL;
+    const StatePlan plan = state_plan(grid, lattice, species, o);
+    *bytes = (int64_t)plan.elem * plan.elems;
+    return LBM_OK;
+}
+
+int lbm_equilibrium_moments(lbm_ctx *c, const lbm_fields *primitive, lbm_fields *moments)
+{
+    if (!c) return LBM_EINVAL;
+    c->err.clear();
+    const int np = c->species + 3, nm = public_fields(c);
+    int rc = check_fields(c, primitive, np);
+    if (!rc) rc = check_fields(c, moments, nm);
+    if (rc) return rc;
+    DeviceGuard g(c->device);
+    const void *src = nullptr;
+    void *in_owned = nullptr, *dst = nullptr, *out_owned = nullptr;
+    if ((rc = stage_in(c, primitive, np, &src, &in_owned))) return rc;
+    if ((rc = stage_out(c, moments, nm, &dst, &out_owned))) {
+        if (in_owned) (void)hipFree(in_owned);
+        return rc;
+    }
+    hipError_t e = lbm::launch_equilibrium(c, src, primitive->field_stride, primitive->dtype, dst,
+                                           moments->field_stride, moments->dtype);
+    e = finish_io(c, e, moments, nm, out_owned, in_owned);
+    if (e != hipSuccess) return hip_fail(c, e, "equilibrium_moments");
+    return LBM_OK;
+}
+
+int lbm_equilibrium_moments_adjoint(lbm_ctx *c, const lbm_fields *primitive, const lbm_fields *grad_moments,
+                                    lbm_fields *grad_primitive)
+{
+    if (!c) return LBM_EINVAL;
+    c->err.clear();
+    const int np = c->species + 3, nm = public_fields(c);
+    int rc = check_fields(c, primitive, np);
+    if (!rc) rc = check_fields(c, grad_moments, nm);
+    if (!rc) rc = check_fields(c, grad_primitive, np);
+    if (rc) return rc;
+    DeviceGuard g(c->device);
+    const void *prim = nullptr, *grad = nullptr;
+    void *p_owned = nullptr, *g_owned = nullptr, *dst = nullptr, *out_owned = nullptr;
+    if ((rc = stage_in(c, primitive, np, &prim, &p_owned))) return rc;
+    if ((rc = stage_in(c, grad_moments, nm, &grad, &g_owned)) ||
+        (rc = stage_out(c, grad_primitive, np, &dst, &out_owned))) {
+        if (p_owned) (void)hipFree(p_owned);
+        if (g_owned) (void)hipFree(g_owned);
+        return rc;
+    }
+    hipError_t e = lbm::launch_equilibrium_adjoint(c, prim, primitive->field_stride, primitive->dtype, grad,
+                                                   grad_moments->field_stride, grad_moments->dtype, dst,
+                                                   grad_primitive->field_stride, grad_primitive->dtype);
+    e = finish_io(c, e, grad_primitive, np, out_owned, p_owned, g_owned);
+    if (e != hipSuccess) return hip_fail(c, e, "equilibrium_moments_adjoint");
+    return LBM_OK;
+}
+
 int lbm_save_state(lbm_ctx *c, void *dst)
 {
     if (!c) return LBM_EINVAL;
@@ -503,19 +653,16 @@ int lbm_adjoint_step2_stored(lbm_ctx *c, const void *state_t1, const void *state
     return LBM_OK;
 }
 
-static int adjoint_step(lbm_ctx *c, const void *state, const void *lam_next, void *lam_out, double *dtau_accum,
-                        bool stored)
+static size_t real_bytes(const lbm_ctx *c) { return c->storage == LBM_STORE_F64 ? 8 : 4; }
+
+// Validation shared by the adjoint entry points, and the colour-gradient
+// co-state buffer the two-species adjoint needs (allocated on first use).
+static int adjoint_ready(lbm_ctx *c)
 {
-    if (!c) return LBM_EINVAL;
-    if (!state || !lam_next || !lam_out || lam_next == lam_out)
-        return fail(c, LBM_EINVAL, "adjoint_step: NULL or aliased buffers");
-    if (c->scheme != LBM_SCHEME_MOMENT)
-        return fail(c, LBM_ESTATE, "adjoint_step: moment scheme only");
+    if (c->scheme != LBM_SCHEME_MOMENT) return fail(c, LBM_ESTATE, "adjoint_step: moment scheme only");
     if (c->species == 2 && c->storage != LBM_STORE_F32 && c->storage != LBM_STORE_F64)
         return fail(c, LBM_ESTATE, "adjoint_step: two species need FP32 or FP64 storage");
     if (c->nc_A != 0.0) return fail(c, LBM_ESTATE, "adjoint_step: not with the near-contact force");
-    c->err.clear();
-    DeviceGuard g(c->device);
     if (c->species == 2 && !c->scratch_adj) {
         if (hipMalloc(&c->scratch_adj, c->elem * (size_t)(c->lay3.plane * c->nz)) != hipSuccess) {
             c->scratch_adj = nullptr;
@@ -523,24 +670,77 @@ static int adjoint_step(lbm_ctx *c, const void *state, const void *lam_next, voi
             return fail(c, LBM_ENOMEM, "adjoint_step: colour-gradient co-state buffer");
         }
     }
-    hipError_t e = c->species == 2 ? lbm::launch_cg_adjoint_step(c, state, lam_next, lam_out, dtau_accum, stored)
-                                   : lbm::launch_adjoint_step(c, state, lam_next, lam_out, dtau_accum, stored);
-    if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
     return LBM_OK;
 }
 
-int lbm_adjoint_step(lbm_ctx *c, const void *state, const void *lam_next, void *lam_out, double *dtau_accum)
+int lbm_adjoint_step(lbm_ctx *c, const lbm_fields *state_t, const lbm_fields *lam_next, lbm_fields *lam_out,
+                     double *dtau_accum)
 {
-    return adjoint_step(c, state, lam_next, lam_out, dtau_accum, false);
+    if (!c) return LBM_EINVAL;
+    c->err.clear();
+    const int nf = public_fields(c);
+    int rc = check_fields(c, state_t, nf);
+    if (!rc) rc = check_fields(c, lam_next, nf);
+    if (!rc) rc = check_fields(c, lam_out, nf);
+    if (rc) return rc;
+    if (lam_next->base == lam_out->base) return fail(c, LBM_EINVAL, "adjoint_step: lam_out aliases lam_next");
+    DeviceGuard g(c->device);
+    if ((rc = adjoint_ready(c))) return rc;
+    // Work area kept by the context: the state in its stored format and the
+    // two co-states in the stored layout, then one double for dL/dtau.
+    const size_t st_bytes = (c->elem * (size_t)c->state_elems + 255) / 256 * 256;
+    const size_t co_bytes = (real_bytes(c) * (size_t)c->state_elems + 255) / 256 * 256;
+    if (!c->adj_work) {
+        if (hipMalloc(&c->adj_work, st_bytes + 2 * co_bytes) != hipSuccess ||
+            hipMalloc((void **)&c->adj_dtau, sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            if (c->adj_work) (void)hipFree(c->adj_work);
+            c->adj_work = nullptr;
+            c->adj_dtau = nullptr;
+            return fail(c, LBM_ENOMEM, "adjoint_step: work area");
+        }
+    }
+    char *w = static_cast<char *>(c->adj_work);
+    void *st = w, *co_in = w + st_bytes, *co_out = w + st_bytes + co_bytes;
+    const void *s_dev = nullptr, *l_dev = nullptr;
+    void *s_owned = nullptr, *l_owned = nullptr, *o_dev = nullptr, *o_owned = nullptr;
+    if ((rc = stage_in(c, state_t, nf, &s_dev, &s_owned))) return rc;
+    if ((rc = stage_in(c, lam_next, nf, &l_dev, &l_owned)) || (rc = stage_out(c, lam_out, nf, &o_dev, &o_owned))) {
+        if (s_owned) (void)hipFree(s_owned);
+        if (l_owned) (void)hipFree(l_owned);
+        return rc;
+    }
+    hipError_t e = lbm::launch_set_moments(c, s_dev, state_t->field_stride, state_t->dtype, st);
+    if (e == hipSuccess) e = lbm::launch_costate_convert(c, l_dev, co_in, true, lam_next->field_stride, lam_next->dtype);
+    if (e == hipSuccess && dtau_accum) e = hipMemsetAsync(c->adj_dtau, 0, sizeof(double), c->stream);
+    if (e == hipSuccess)
+        e = c->species == 2 ? lbm::launch_cg_adjoint_step(c, st, co_in, co_out, dtau_accum ? c->adj_dtau : nullptr, true)
+                            : lbm::launch_adjoint_step(c, st, co_in, co_out, dtau_accum ? c->adj_dtau : nullptr, true);
+    if (e == hipSuccess)
+        e = lbm::launch_costate_convert(c, co_out, o_dev, false, lam_out->field_stride, lam_out->dtype);
+    double d = 0.0;
+    if (e == hipSuccess && dtau_accum) e = hipMemcpyAsync(&d, c->adj_dtau, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && dtau_accum && !o_owned && !s_owned && !l_owned) e = hipStreamSynchronize(c->stream);
+    e = finish_io(c, e, lam_out, nf, o_owned, s_owned, l_owned);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
+    if (dtau_accum) *dtau_accum += d;
+    return LBM_OK;
 }
 
 int lbm_adjoint_step_stored(lbm_ctx *c, const void *state, const void *lam_next, void *lam_out, double *dtau_accum)
 {
-    return adjoint_step(c, state, lam_next, lam_out, dtau_accum, true);
+    if (!c) return LBM_EINVAL;
+    if (!state || !lam_next || !lam_out || lam_next == lam_out)
+        return fail(c, LBM_EINVAL, "adjoint_step: NULL or aliased buffers");
+    c->err.clear();
+    DeviceGuard g(c->device);
+    int rc = adjoint_ready(c);
+    if (rc) return rc;
+    hipError_t e = c->species == 2 ? lbm::launch_cg_adjoint_step(c, state, lam_next, lam_out, dtau_accum, true)
+                                   : lbm::launch_adjoint_step(c, state, lam_next, lam_out, dtau_accum, true);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
+    return LBM_OK;
 }
-
-static size_t real_bytes(const lbm_ctx *c) { return c->storage == LBM_STORE_F64 ? 8 : 4; }
-
 int lbm_costate_bytes(const lbm_ctx *c, int64_t *bytes)
 {
     if (!c || !bytes) return LBM_EINVAL;

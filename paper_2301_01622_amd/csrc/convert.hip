@@ -92,17 +92,23 @@ __global__ void k_get_moment_state(const S *__restrict__ st, T *__restrict__ dst
 
 // ---- co-states ----------------------------------------------------------------
 
-template <class R>
-__global__ void k_costate_convert(const R *__restrict__ src, R *__restrict__ dst, int64_t N, int nx, int ny,
-                                  MomentLayout lay, int nf, bool to_stored)
+// Public layout: field k at pub + k*stride (element type P); stored layout:
+// the blocked layout of the state with the kernels' real type R.
+template <class P, class R>
+__global__ void k_costate_convert(const void *__restrict__ src, void *__restrict__ dst, int64_t stride, int64_t N,
+                                  int nx, int ny, MomentLayout lay, int nf, bool to_stored)
 {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     const int64_t so = stored_node(lay, n, nx, ny);
     if (to_stored) {
-        for (int k = 0; k < nf; ++k) dst[k * kBlock + so] = src[k * N + n];
+        const P *s = static_cast<const P *>(src);
+        R *d = static_cast<R *>(dst);
+        for (int k = 0; k < nf; ++k) d[k * kBlock + so] = (R)s[k * stride + n];
     } else {
-        for (int k = 0; k < nf; ++k) dst[k * N + n] = src[k * kBlock + so];
+        const R *s = static_cast<const R *>(src);
+        P *d = static_cast<P *>(dst);
+        for (int k = 0; k < nf; ++k) d[k * stride + n] = (P)s[k * kBlock + so];
     }
 }
 
@@ -241,11 +247,16 @@ __global__ void k_get_population2_state(const float *__restrict__ A, T *__restri
     dst[10 * stride + n] = (T)a.myz;
 }
 
-// ---- primitive fields -> equilibrium moments (public layout, FP64) -------------
+// ---- primitive fields -> equilibrium moments (public layout) ---------------------
+//
+// M = (rho^k, rho u, rho c_s^2 I + rho u u): the moments of the equilibrium
+// populations of Eq. 5 (zero non-equilibrium part), FP64 arithmetic, rounded
+// once at the store.  Primitive fields: rho (one species) or rho1, rho2, then
+// ux, uy, uz.
 
-template <class T>
-__global__ void k_primitive_to_moments(const T *__restrict__ src, int64_t stride, double *__restrict__ pub,
-                                       int64_t N, int species)
+template <class T, class O>
+__global__ void k_primitive_to_moments(const T *__restrict__ src, int64_t stride, O *__restrict__ pub,
+                                       int64_t ostride, int64_t N, int species)
 {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
@@ -253,21 +264,60 @@ __global__ void k_primitive_to_moments(const T *__restrict__ src, int64_t stride
     int off;
     if (species == 1) {
         rho = (double)src[n];
-        pub[n] = rho;
+        pub[n] = (O)rho;
         off = 1;
     } else {
         const double r1 = (double)src[n], r2 = (double)src[stride + n];
         rho = r1 + r2;
-        pub[n] = r1;
-        pub[N + n] = r2;
+        pub[n] = (O)r1;
+        pub[ostride + n] = (O)r2;
         off = 2;
     }
     double u[3];
     for (int a = 0; a < 3; ++a) u[a] = (double)src[(off + a) * stride + n];
-    for (int a = 0; a < 3; ++a) pub[(off + a) * N + n] = rho * u[a];
+    for (int a = 0; a < 3; ++a) pub[(off + a) * ostride + n] = (O)(rho * u[a]);
     const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
     for (int k = 0; k < 6; ++k)
-        pub[(off + 3 + k) * N + n] = rho * u[pa[k]] * u[pb[k]] + (k < 3 ? rho / 3.0 : 0.0);
+        pub[(off + 3 + k) * ostride + n] = (O)(rho * u[pa[k]] * u[pb[k]] + (k < 3 ? rho / 3.0 : 0.0));
+}
+
+// Transpose of the Jacobian of the map above at the primitive fields `src`,
+// applied to the moment gradient g (public layout): with g_j and g_P the
+// gradients of j and of the six stored P components,
+//   dL/drho^k = g_rho^k + u.g_j + sum_ab g_P_ab (u_a u_b + delta_ab/3),
+//   dL/du_c   = rho g_j_c + rho sum_ab g_P_ab (delta_ac u_b + u_a delta_bc),
+// a stored off-diagonal component counting once.  FP64 arithmetic.
+template <class T, class G, class O>
+__global__ void k_primitive_to_moments_adjoint(const T *__restrict__ src, int64_t stride, const G *__restrict__ g,
+                                               int64_t gstride, O *__restrict__ out, int64_t ostride, int64_t N,
+                                               int species)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int off = species == 1 ? 1 : 2;
+    const double rho = species == 1 ? (double)src[n] : (double)src[n] + (double)src[stride + n];
+    double u[3], gj[3], gp[6];
+    for (int a = 0; a < 3; ++a) {
+        u[a] = (double)src[(off + a) * stride + n];
+        gj[a] = (double)g[(off + a) * gstride + n];
+    }
+    for (int k = 0; k < 6; ++k) gp[k] = (double)g[(off + 3 + k) * gstride + n];
+    // Shared part of the density gradient (every species enters through rho).
+    const double grho = u[0] * gj[0] + u[1] * gj[1] + u[2] * gj[2] + gp[0] * (u[0] * u[0] + 1.0 / 3.0) +
+                        gp[1] * (u[1] * u[1] + 1.0 / 3.0) + gp[2] * (u[2] * u[2] + 1.0 / 3.0) +
+                        gp[3] * u[0] * u[1] + gp[4] * u[0] * u[2] + gp[5] * u[1] * u[2];
+    if (species == 1) {
+        out[n] = (O)((double)g[n] + grho);
+    } else {
+        out[n] = (O)((double)g[n] + grho);
+        out[ostride + n] = (O)((double)g[gstride + n] + grho);
+    }
+    const double gux = gj[0] + 2.0 * gp[0] * u[0] + gp[3] * u[1] + gp[4] * u[2];
+    const double guy = gj[1] + 2.0 * gp[1] * u[1] + gp[3] * u[0] + gp[5] * u[2];
+    const double guz = gj[2] + 2.0 * gp[2] * u[2] + gp[4] * u[0] + gp[5] * u[1];
+    out[off * ostride + n] = (O)(rho * gux);
+    out[(off + 1) * ostride + n] = (O)(rho * guy);
+    out[(off + 2) * ostride + n] = (O)(rho * guz);
 }
 
 // ---- FP64 totals -------------------------------------------------------------------
@@ -435,19 +485,53 @@ hipError_t launch_get_moments(const lbm_ctx *c, const void *state, void *dst, in
     });
 }
 
+// Calls f((T*)nullptr) with T the element type of a caller buffer.
+template <class F>
+hipError_t with_dtype(int dtype, F &&f)
+{
+    return dtype == LBM_DTYPE_F64 ? f((double *)nullptr) : f((float *)nullptr);
+}
+
+hipError_t launch_equilibrium(const lbm_ctx *c, const void *src, int64_t stride, int dtype, void *dst,
+                              int64_t dstride, int ddtype)
+{
+    return with_dtype(dtype, [&](auto *t) -> hipError_t {
+        using T = std::remove_pointer_t<decltype(t)>;
+        return with_dtype(ddtype, [&](auto *o) -> hipError_t {
+            using O = std::remove_pointer_t<decltype(o)>;
+            hipLaunchKernelGGL((k_primitive_to_moments<T, O>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
+                               static_cast<const T *>(src), stride, static_cast<O *>(dst), dstride, c->N, c->species);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t launch_equilibrium_adjoint(const lbm_ctx *c, const void *prim, int64_t pstride, int pdtype,
+                                      const void *grad, int64_t gstride, int gdtype, void *out, int64_t ostride,
+                                      int odtype)
+{
+    return with_dtype(pdtype, [&](auto *t) -> hipError_t {
+        using T = std::remove_pointer_t<decltype(t)>;
+        return with_dtype(gdtype, [&](auto *gt) -> hipError_t {
+            using G = std::remove_pointer_t<decltype(gt)>;
+            return with_dtype(odtype, [&](auto *o) -> hipError_t {
+                using O = std::remove_pointer_t<decltype(o)>;
+                hipLaunchKernelGGL((k_primitive_to_moments_adjoint<T, G, O>), dim3(blocks_for(c->N)), dim3(kThreads),
+                                   0, c->stream, static_cast<const T *>(prim), pstride, static_cast<const G *>(grad),
+                                   gstride, static_cast<O *>(out), ostride, c->N, c->species);
+                return hipGetLastError();
+            });
+        });
+    });
+}
+
 hipError_t launch_set_equilibrium(const lbm_ctx *c, const void *src, int64_t stride, int dtype, void *state)
 {
     const int nf = c->species == 1 ? 10 : 11;
     double *pub = nullptr;
     hipError_t e = hipMallocAsync((void **)&pub, sizeof(double) * nf * c->N, c->stream);
     if (e != hipSuccess) return e;
-    if (dtype == LBM_DTYPE_F64)
-        hipLaunchKernelGGL((k_primitive_to_moments<double>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
-                           static_cast<const double *>(src), stride, pub, c->N, c->species);
-    else
-        hipLaunchKernelGGL((k_primitive_to_moments<float>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
-                           static_cast<const float *>(src), stride, pub, c->N, c->species);
-    e = hipGetLastError();
+    e = launch_equilibrium(c, src, stride, dtype, pub, c->N, LBM_DTYPE_F64);
     if (e == hipSuccess) e = launch_set_moments(c, pub, c->N, LBM_DTYPE_F64, state);
     hipError_t e2 = hipFreeAsync(pub, c->stream);
     return e != hipSuccess ? e : e2;
@@ -481,17 +565,21 @@ hipError_t launch_reduce(const lbm_ctx *c, const void *state)
     return hipGetLastError();
 }
 
-hipError_t launch_costate_convert(const lbm_ctx *c, const void *src, void *dst, bool to_stored)
+hipError_t launch_costate_convert(const lbm_ctx *c, const void *src, void *dst, bool to_stored, int64_t stride,
+                                  int pub_dtype)
 {
-    if (c->storage == LBM_STORE_F64)
-        hipLaunchKernelGGL((k_costate_convert<double>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
-                           static_cast<const double *>(src), static_cast<double *>(dst), c->N, c->nx, c->ny, c->lay,
-                           c->nfields, to_stored);
-    else
-        hipLaunchKernelGGL((k_costate_convert<float>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
-                           static_cast<const float *>(src), static_cast<float *>(dst), c->N, c->nx, c->ny, c->lay,
-                           c->nfields, to_stored);
-    return hipGetLastError();
+    if (stride <= 0) stride = c->N;
+    if (pub_dtype < 0) pub_dtype = c->storage == LBM_STORE_F64 ? LBM_DTYPE_F64 : LBM_DTYPE_F32;
+    return with_dtype(pub_dtype, [&](auto *pt) -> hipError_t {
+        using P = std::remove_pointer_t<decltype(pt)>;
+        if (c->storage == LBM_STORE_F64)
+            hipLaunchKernelGGL((k_costate_convert<P, double>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
+                               src, dst, stride, c->N, c->nx, c->ny, c->lay, c->nfields, to_stored);
+        else
+            hipLaunchKernelGGL((k_costate_convert<P, float>), dim3(blocks_for(c->N)), dim3(kThreads), 0, c->stream,
+                               src, dst, stride, c->N, c->nx, c->ny, c->lay, c->nfields, to_stored);
+        return hipGetLastError();
+    });
 }
 
 } // namespace lbm

@@ -34,6 +34,9 @@ struct lbm_ctx {
     double *red_out = nullptr;   // 5 device doubles
     float *scratch_phi = nullptr; // phase field of the two-species population scheme
     void *scratch_adj = nullptr;  // co-state of the colour gradient (3 fields, layout lay3), two-species adjoint
+    void *adj_work = nullptr;     // lbm_adjoint_step: one stored state and two stored co-states
+    double *adj_dtau = nullptr;   // lbm_adjoint_step: its dL/dtau term (one device double)
+    bool owns_state = true;       // false: the state copies are caller buffers (lbm_opts.state_buffers)
     int64_t steps = 0;
     mutable std::string err;
 };
@@ -77,9 +80,12 @@ hipError_t launch_adjoint_step(const lbm_ctx *c, const void *state, const void *
 hipError_t launch_cg_adjoint_step(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out,
                                   double *dtau_accum, bool stored);
 
-// Co-state (real type of the context, nfields fields) between the public
-// layout (nfields x N) and the stored blocked layout (state_elems elements).
-hipError_t launch_costate_convert(const lbm_ctx *c, const void *src, void *dst, bool to_stored);
+// Co-state between the public layout (nfields fields, field k at
+// base + k*stride, elements of pub_dtype; stride <= 0: N, pub_dtype < 0: the
+// kernels' real type) and the stored blocked layout (state_elems elements of
+// the kernels' real type).
+hipError_t launch_costate_convert(const lbm_ctx *c, const void *src, void *dst, bool to_stored, int64_t stride = 0,
+                                  int pub_dtype = -1);
 
 // Near-contact force of the two-species schemes into c->scratch_nc (three
 // arrays of N), from the phase field `phi` (N values, population scheme) or,
@@ -98,6 +104,15 @@ hipError_t launch_population_step(const lbm_ctx *c, const void *in, void *out);
 hipError_t launch_set_moments(const lbm_ctx *c, const void *src, int64_t stride, int dtype, void *state);
 hipError_t launch_get_moments(const lbm_ctx *c, const void *state, void *dst, int64_t stride, int dtype);
 hipError_t launch_set_equilibrium(const lbm_ctx *c, const void *src, int64_t stride, int dtype, void *state);
+
+// Equilibrium moments of primitive fields (rho^k, u) into a public-layout
+// buffer (field stride dstride, element type ddtype), and the transpose of
+// that map's Jacobian at `prim` applied to a moment gradient `grad`.
+hipError_t launch_equilibrium(const lbm_ctx *c, const void *src, int64_t stride, int dtype, void *dst,
+                              int64_t dstride, int ddtype);
+hipError_t launch_equilibrium_adjoint(const lbm_ctx *c, const void *prim, int64_t pstride, int pdtype,
+                                      const void *grad, int64_t gstride, int gdtype, void *out, int64_t ostride,
+                                      int odtype);
 
 // Streaming device-to-device copy of `bytes` bytes (16-byte vector accesses).
 hipError_t launch_copy(const lbm_ctx *c, const void *src, void *dst, int64_t bytes);

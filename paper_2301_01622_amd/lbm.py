@@ -28,7 +28,7 @@ class LBM:
                  scheme: str = "moment", storage: str = "f32", beta: float = 0.7, sigma: float = 0.01,
                  s_pi: float = 0.0, device: int = 0, stream: torch.cuda.Stream | None = None,
                  check_every: int = 0, split: bool = False, steps_per_sweep: int = 0, nc_A: float = 0.0,
-                 nc_hmax: int = 0):
+                 nc_hmax: int = 0, state_buffers=None):
         lib = _lib.load()
         self.nx, self.ny, self.nz = (int(s) for s in shape)
         self.q, self.tau, self.species = int(lattice), float(tau), int(species)
@@ -50,12 +50,40 @@ class LBM:
         opts.steps_per_sweep = int(steps_per_sweep)
         opts.nc_A = float(nc_A)
         opts.nc_hmax = int(nc_hmax)
+        if state_buffers is not None:
+            # Caller-owned state copies (torch device tensors of at least
+            # state_bytes_for() bytes each); kept alive with the context.
+            bufs = list(state_buffers)
+            nbytes = min(b.numel() * b.element_size() for b in bufs)
+            for k, b in enumerate(bufs[:2]):
+                assert b.is_cuda and b.is_contiguous()
+                opts.state_buffers[k] = b.data_ptr()
+            opts.state_buffer_bytes = nbytes
+            self._state_buffers = bufs
         ctx = ctypes.c_void_p()
         rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(self.nx, self.ny, self.nz), self.q, self.tau,
                             self.species, ctypes.byref(opts))
         _lib.check(rc, None, "lbm_create")
         self._ctx = ctx
         self._lib = lib
+
+    @staticmethod
+    def state_bytes_for(shape, lattice: int = 19, species: int = 1, *, scheme: str = "moment",
+                        storage: str = "f32", split: bool = False, steps_per_sweep: int = 0) -> int:
+        """Bytes of one state copy a context of this setup uses (the size of
+        each caller buffer passed as state_buffers)."""
+        lib = _lib.load()
+        opts = _lib.Opts()
+        lib.lbm_default_opts(ctypes.byref(opts))
+        opts.scheme = _lib.SCHEME[scheme]
+        opts.storage = _lib.STORAGE[storage]
+        opts.split = int(bool(split))
+        opts.steps_per_sweep = int(steps_per_sweep)
+        b = ctypes.c_int64()
+        nx, ny, nz = (int(v) for v in shape)
+        _lib.check(lib.lbm_state_bytes_for(_lib.Grid(nx, ny, nz), int(lattice), int(species), ctypes.byref(opts),
+                                           ctypes.byref(b)), None, "state_bytes_for")
+        return b.value
 
     # ---- properties -------------------------------------------------------
     @property
@@ -175,16 +203,47 @@ class LBM:
         """Arithmetic type of the kernels (the co-state's element type)."""
         return torch.float64 if self.storage == "f64" else torch.float32
 
-    def adjoint_step(self, state: torch.Tensor, lam_next: torch.Tensor, lam_out: torch.Tensor,
-                     dtau_accum: torch.Tensor | None = None) -> None:
-        """lam_out = (dM(t+1)/dM(t))^T lam_next at the saved state M(t);
-        adds this step's dL/dtau into dtau_accum (one float64 on the device)."""
-        assert lam_next.dtype == self.real_dtype and lam_out.dtype == self.real_dtype
-        assert lam_next.is_contiguous() and lam_out.is_contiguous()
-        dptr = ctypes.c_void_p(dtau_accum.data_ptr()) if dtau_accum is not None else None
-        _lib.check(self._lib.lbm_adjoint_step(self._ctx, ctypes.c_void_p(state.data_ptr()),
-                                              ctypes.c_void_p(lam_next.data_ptr()),
-                                              ctypes.c_void_p(lam_out.data_ptr()), dptr), self._ctx, "adjoint_step")
+    def adjoint_step(self, state_t, lam_next, lam_out, dtau: float | None = None) -> float | None:
+        """lam_out = (dM(t+1)/dM(t))^T lam_next at the state M(t) given as public
+        moments; all three (nfields, nz, ny, nx) float32/float64, torch (host
+        or device) or numpy.  Returns dtau + this step's dL/dtau if dtau is
+        given (a float), else None."""
+        for t in (state_t, lam_next, lam_out):
+            assert tuple(t.shape) == (self.nfields,) + self.shape, t.shape
+        fs, fl, fo = self._fields(state_t), self._fields(lam_next), self._fields(lam_out)
+        acc = ctypes.c_double(0.0 if dtau is None else float(dtau))
+        _lib.check(self._lib.lbm_adjoint_step(self._ctx, ctypes.byref(fs), ctypes.byref(fl), ctypes.byref(fo),
+                                              ctypes.byref(acc) if dtau is not None else None),
+                   self._ctx, "adjoint_step")
+        return acc.value if dtau is not None else None
+
+    # ---- the equilibrium map (initial fields -> initial moments) ------------
+    def _prim_shape(self):
+        return (self.species + 3,) + self.shape
+
+    def equilibrium(self, prim, out=None):
+        """Public moments (rho^k, rho u, rho c_s^2 I + rho u u) of the primitive
+        fields prim = (rho | rho1, rho2, ux, uy, uz), shape (species+3, nz, ny,
+        nx); the context's state is not touched."""
+        assert tuple(prim.shape) == self._prim_shape(), prim.shape
+        if out is None:
+            out = torch.empty((self.nfields,) + self.shape, dtype=prim.dtype, device=prim.device)
+        fi, fo = self._fields(prim), self._fields(out)
+        _lib.check(self._lib.lbm_equilibrium_moments(self._ctx, ctypes.byref(fi), ctypes.byref(fo)), self._ctx,
+                   "equilibrium_moments")
+        return out
+
+    def equilibrium_adjoint(self, prim, grad_moments, out=None):
+        """Transpose of the Jacobian of equilibrium() at prim applied to a
+        gradient with respect to the moments: dL/d(rho^k, u)."""
+        assert tuple(prim.shape) == self._prim_shape(), prim.shape
+        assert tuple(grad_moments.shape) == (self.nfields,) + self.shape, grad_moments.shape
+        if out is None:
+            out = torch.empty(self._prim_shape(), dtype=prim.dtype, device=prim.device)
+        fp, fg, fo = self._fields(prim), self._fields(grad_moments), self._fields(out)
+        _lib.check(self._lib.lbm_equilibrium_moments_adjoint(self._ctx, ctypes.byref(fp), ctypes.byref(fg),
+                                                             ctypes.byref(fo)), self._ctx, "equilibrium_moments_adjoint")
+        return out
 
     # ---- co-states in the stored layout -----------------------------------
     @property

@@ -170,3 +170,50 @@ def test_create_rejects_s_pi_where_not_applied(species, scheme, storage, s_pi):
     rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(8, 8, 8), 19, 0.8, species, ctypes.byref(opts))
     assert rc == _lib.LBM_EINVAL
     assert not ctx.value
+
+
+@pytest.mark.parametrize("grid,q,species,scheme,storage,expect", [
+    # moment scheme: blocked layout, nx and ny rounded up to 64 and 16
+    ((64, 16, 4), 27, 1, 0, 1, 64 * 16 * 4 * 10 * 4),
+    ((37, 23, 19), 19, 1, 0, 1, 64 * 32 * 19 * 10 * 4),
+    ((37, 23, 19), 19, 2, 0, 0, 64 * 32 * 19 * 11 * 8),
+    ((130, 17, 5), 27, 1, 0, 2, 192 * 32 * 5 * 10 * 2),
+    # population schemes: q (two species 2q) arrays of N values
+    ((37, 23, 19), 27, 1, 1, 1, 27 * 37 * 23 * 19 * 4),
+    ((37, 23, 19), 19, 2, 1, 1, 38 * 37 * 23 * 19 * 4),
+    ((37, 23, 19), 19, 1, 2, 0, 19 * 37 * 23 * 19 * 8),
+])
+def test_state_bytes_for_without_a_context(grid, q, species, scheme, storage, expect):
+    """lbm_state_bytes_for: the size of one state copy of a setup (the size
+    caller-owned state buffers need), computed on the host."""
+    lib = _lib.load()
+    opts = _lib.Opts()
+    lib.lbm_default_opts(ctypes.byref(opts))
+    assert not opts.state_buffers[0] and not opts.state_buffers[1] and opts.state_buffer_bytes == 0
+    opts.scheme, opts.storage = scheme, storage
+    b = ctypes.c_int64(-1)
+    assert lib.lbm_state_bytes_for(_lib.Grid(*grid), q, species, ctypes.byref(opts), ctypes.byref(b)) == _lib.LBM_OK
+    assert b.value == expect
+    # the same validation as lbm_create
+    assert lib.lbm_state_bytes_for(_lib.Grid(2, 8, 8), q, species, ctypes.byref(opts), ctypes.byref(b)) == \
+        _lib.LBM_EINVAL
+    assert lib.lbm_state_bytes_for(_lib.Grid(*grid), q, species, ctypes.byref(opts), None) == _lib.LBM_EINVAL
+
+
+@pytest.mark.parametrize("which", ["one_missing", "same_twice", "too_small"])
+def test_create_rejects_bad_state_buffers_before_device(which):
+    """Caller-owned state buffers: both or none, distinct, and each at least
+    lbm_state_bytes_for() bytes; refused before any device work (the
+    pointers are never dereferenced on this path)."""
+    lib = _lib.load()
+    opts = _lib.Opts()
+    lib.lbm_default_opts(ctypes.byref(opts))
+    need = ctypes.c_int64()
+    assert lib.lbm_state_bytes_for(_lib.Grid(8, 8, 8), 19, 1, ctypes.byref(opts), ctypes.byref(need)) == 0
+    opts.state_buffers[0] = 0x1000
+    opts.state_buffers[1] = {"one_missing": 0, "same_twice": 0x1000, "too_small": 0x2000}[which]
+    opts.state_buffer_bytes = need.value - (1 if which == "too_small" else 0)
+    ctx = ctypes.c_void_p(123)
+    rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(8, 8, 8), 19, 0.8, 1, ctypes.byref(opts))
+    assert rc == _lib.LBM_EINVAL
+    assert not ctx.value

@@ -31,24 +31,27 @@ def _rel(a, b):
 
 @pytest.mark.parametrize("q", [19, 27])
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
-def test_adjoint_step_matches_oracle(mods, oracle, q, storage, tol):
+@pytest.mark.parametrize("where", ["device", "host"])
+def test_adjoint_step_matches_oracle(mods, oracle, q, storage, tol, where):
+    """lbm_adjoint_step at the boundary: state M(t) and co-states as public
+    moments, in device memory (the kernels' real type) or in host memory
+    (FP64 numpy arrays), dL/dtau accumulated into a host double."""
     LBM, _ = mods
     shape = (19, 23, 37)
-    _say(f"adjoint step {shape} D3Q{q} {storage}")
+    _say(f"adjoint step {shape} D3Q{q} {storage} buffers on the {where}")
     M = I.random_moments(shape, seed=91)
     lam = np.random.default_rng(92).standard_normal(M.shape)
     tau = 0.66
     ref, dom = oracle.moment_adjoint_step(M, lam, q, tau)
     sim = LBM((37, 23, 19), q, tau, storage=storage)
-    sim.set_moments(torch.from_numpy(M).cuda())
-    st = sim.new_checkpoint()
-    sim.save_state(st)
-    ln = torch.from_numpy(lam).to(sim.real_dtype).cuda().contiguous()
-    lo = torch.empty_like(ln)
-    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
-    sim.adjoint_step(st, ln, lo, dt)
-    got = lo.double().cpu().numpy()
-    dtau = float(dt.cpu())
+    if where == "device":
+        st = torch.from_numpy(M).cuda()
+        ln = torch.from_numpy(lam).to(sim.real_dtype).cuda().contiguous()
+        lo = torch.empty_like(ln)
+    else:
+        st, ln, lo = M, lam, np.empty_like(lam)
+    dtau = sim.adjoint_step(st, ln, lo, dtau=1.0) - 1.0
+    got = lo.double().cpu().numpy() if where == "device" else lo
     sim.close()
     e = _rel(got, ref)
     _say(f"  rel err {e:.3e}, dL/dtau gpu {dtau:.10e} oracle {-dom / tau ** 2:.10e}")
@@ -120,8 +123,7 @@ def test_rollout_gradient_finite_differences(mods):
         sim = LBM((n, n, n), 19, float(t), storage="f32")
         u = torch.from_numpy(u).cuda().requires_grad_(grad)
         tt = torch.tensor(float(t), dtype=torch.float64, device="cuda", requires_grad=grad)
-        M0 = AG.equilibrium_moments(rho_t, u)
-        MT = AG.rollout(sim, M0, tt, T, K=K)
+        MT = AG.MomentLBRollout.apply(rho_t, u, tt, sim, T, K)
         L = (mask * (MT[1] ** 2 + MT[2] ** 2 + MT[3] ** 2) / MT[0]).sum()
         if grad:
             L.backward()
@@ -158,13 +160,13 @@ def test_adjoint_step_stored_layout_bitwise(mods, oracle, species, storage):
         M = oracle.equilibrium_moments2(r1, r2, u)
     lam = np.random.default_rng(96).standard_normal(M.shape)
     sim = LBM((37, 23, 19), 19, 0.7, species=species, storage=storage, sigma=0.01, beta=0.7)
-    sim.set_moments(torch.from_numpy(M).cuda())
+    Md = torch.from_numpy(M).cuda()
+    sim.set_moments(Md)
     st = sim.new_checkpoint()
     sim.save_state(st)
     ln = torch.from_numpy(lam).to(sim.real_dtype).cuda().contiguous()
     lo = torch.empty_like(ln)
-    d_pub = torch.zeros(1, dtype=torch.float64, device="cuda")
-    sim.adjoint_step(st, ln, lo, d_pub)
+    d_pub = sim.adjoint_step(Md, ln, lo, dtau=0.0)
     s_in, s_out = sim.new_costate(), sim.new_costate()
     sim.costate_to_stored(ln, s_in)
     back = torch.empty_like(ln)
@@ -177,7 +179,7 @@ def test_adjoint_step_stored_layout_bitwise(mods, oracle, species, storage):
     sim.close()
     assert torch.equal(back, ln)
     assert torch.equal(lo2, lo)
-    assert float(d_st) == float(d_pub)
+    assert float(d_st) == d_pub
 
 
 def test_adjoint_entry_points_reject_bad_calls(mods):
@@ -195,7 +197,14 @@ def test_adjoint_entry_points_reject_bad_calls(mods):
     ctx = sim._ctx
     assert lib.lbm_adjoint_step_stored(ctx, p(st.data_ptr()), p(lam.data_ptr()), p(lam.data_ptr()), None) == \
         _lib.LBM_EINVAL
-    assert lib.lbm_adjoint_step(ctx, None, p(lam.data_ptr()), p(st.data_ptr()), None) == _lib.LBM_EINVAL
+    pub = torch.zeros((10, 16, 18, 20), device="cuda")
+    f = _lib.Fields(pub.data_ptr(), sim.n_nodes, _lib.DTYPE_F32, 1)
+    g = _lib.Fields(lam.data_ptr(), sim.n_nodes, _lib.DTYPE_F32, 1)
+    assert lib.lbm_adjoint_step(ctx, None, ctypes.byref(f), ctypes.byref(g), None) == _lib.LBM_EINVAL
+    assert lib.lbm_adjoint_step(ctx, ctypes.byref(f), ctypes.byref(g), ctypes.byref(g), None) == _lib.LBM_EINVAL
+    short = _lib.Fields(pub.data_ptr(), sim.n_nodes - 1, _lib.DTYPE_F32, 1)
+    assert lib.lbm_adjoint_step(ctx, ctypes.byref(short), ctypes.byref(f), ctypes.byref(g), None) == \
+        _lib.LBM_EINVAL
     assert lib.lbm_costate_to_stored(ctx, p(lam.data_ptr()), p(lam.data_ptr())) == _lib.LBM_EINVAL
     assert lib.lbm_costate_from_stored(ctx, None, p(lam.data_ptr())) == _lib.LBM_EINVAL
     assert lib.lbm_costate_bytes(ctx, None) == _lib.LBM_EINVAL
@@ -205,7 +214,11 @@ def test_adjoint_entry_points_reject_bad_calls(mods):
     assert lib.lbm_costate_bytes(pop._ctx, ctypes.byref(b)) == _lib.LBM_ESTATE
     buf = torch.zeros(16, device="cuda")
     buf2 = torch.zeros(16, device="cuda")
-    assert lib.lbm_adjoint_step(pop._ctx, p(buf.data_ptr()), p(buf.data_ptr() + 4), p(buf2.data_ptr()), None) == \
+    pa = torch.zeros((10, 16, 18, 20), device="cuda")
+    pb = torch.zeros((10, 16, 18, 20), device="cuda")
+    pc = torch.zeros((10, 16, 18, 20), device="cuda")
+    fa, fb, fc = (_lib.Fields(t.data_ptr(), pop.n_nodes, _lib.DTYPE_F32, 1) for t in (pa, pb, pc))
+    assert lib.lbm_adjoint_step(pop._ctx, ctypes.byref(fa), ctypes.byref(fb), ctypes.byref(fc), None) == \
         _lib.LBM_ESTATE
     assert lib.lbm_costate_to_stored(pop._ctx, p(buf.data_ptr()), p(buf2.data_ptr())) == _lib.LBM_ESTATE
     assert "moment scheme" in lib.lbm_last_error(pop._ctx).decode()

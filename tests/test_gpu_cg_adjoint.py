@@ -50,15 +50,10 @@ def _state(oracle, shape, seed, neq=1e-3, radius=None):
 def _one_step(LBM, H, lam, q, tau, storage, beta=BETA):
     nf, nz, ny, nx = H.shape
     sim = LBM((nx, ny, nz), q, tau, species=2, storage=storage, sigma=SIGMA, beta=beta)
-    sim.set_moments(torch.from_numpy(H).cuda())
-    st = sim.new_checkpoint()
-    sim.save_state(st)
     ln = torch.from_numpy(lam).to(sim.real_dtype).cuda().contiguous()
     lo = torch.empty_like(ln)
-    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
-    sim.adjoint_step(st, ln, lo, dt)
+    dtau = sim.adjoint_step(torch.from_numpy(H).cuda(), ln, lo, dtau=0.0)
     got = lo.double().cpu().numpy()
-    dtau = float(dt.cpu())
     sim.close()
     return got, dtau
 

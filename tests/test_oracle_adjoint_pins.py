@@ -175,3 +175,42 @@ def test_cg_rollout_without_recolouring_long_horizon(oracle):
     fd = (np.sum(W * oracle.cg_moment_run(M0 + h * v, q, tau, A, 0.0, T))
           - np.sum(W * oracle.cg_moment_run(M0 - h * v, q, tau, A, 0.0, T))) / (2 * h)
     assert abs(np.sum(lam0 * v) - fd) <= 1e-6 * abs(fd)
+
+
+@pytest.mark.parametrize("species", [1, 2])
+def test_equilibrium_adjoint_dot_product(oracle, species):
+    """The oracle's chain through the equilibrium map M = (rho^k, rho u,
+    rho c_s^2 I + rho u u) against central differences of the forward map:
+    <J v, w> = <v, J^T w> for random directions v of (rho^k, u) and random
+    moment weights w (the map is quadratic, so the central difference is
+    exact up to rounding)."""
+    shape = (3, 4, 5)
+    rng = np.random.default_rng(71 + species)
+    rho_k = 0.5 + rng.random((species,) + shape)
+    u = 0.1 * rng.standard_normal((3,) + shape)
+    v_rho = rng.standard_normal(rho_k.shape)
+    v_u = rng.standard_normal(u.shape)
+    w = rng.standard_normal((9 + species,) + shape)
+
+    def fwd(r, uu):
+        return oracle.equilibrium_moments(r[0], uu) if species == 1 else oracle.equilibrium_moments2(r[0], r[1], uu)
+
+    eps = 1e-3
+
+    def at(t):
+        return fwd(rho_k + t * v_rho, u + t * v_u)
+
+    Jv = (8 * (at(eps) - at(-eps)) - (at(2 * eps) - at(-2 * eps))) / (12 * eps)
+    JTw = oracle.equilibrium_adjoint(rho_k[0] if species == 1 else rho_k, u, w)
+    lhs = np.sum(Jv * w)
+    rhs = np.sum(v_rho * JTw[:species]) + np.sum(v_u * JTw[species:])
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    # a single component: dP_xy/du_x = rho u_y
+    g = np.zeros_like(w)
+    g[species + 6] = 1.0  # the Pxy weight
+    JT = oracle.equilibrium_adjoint(rho_k[0] if species == 1 else rho_k, u, g)
+    rho = rho_k.sum(0)
+    np.testing.assert_allclose(JT[species], rho * u[1], rtol=1e-15)
+    np.testing.assert_allclose(JT[species + 1], rho * u[0], rtol=1e-15)
+    np.testing.assert_allclose(JT[species + 2], 0.0)
+    np.testing.assert_allclose(JT[0], u[0] * u[1], rtol=1e-15)

@@ -17,6 +17,7 @@ class FakeSim:
 
     def __init__(self, sweeps: bool):
         self.scheme, self.species, self.tau, self.sweeps = "moment", 1, 0.8, sweeps
+        self.nfields, self.shape = 10, (1, 1, 1)
         self.real_dtype = torch.float64
         self.t = 0
         self.reverse = []  # state times the reverse steps linearised about, in order
@@ -36,6 +37,17 @@ class FakeSim:
 
     def get_moments(self, dtype):
         return torch.full((10, 1, 1, 1), float(self.t), dtype=dtype)
+
+    # the equilibrium map: a primitive (rho, u) of all zeros maps to the state
+    # at step 0; its transpose passes the co-state's first entry to every
+    # primitive field
+    def equilibrium(self, prim):
+        assert prim.shape == (4, 1, 1, 1)
+        return torch.zeros((10, 1, 1, 1), dtype=prim.dtype)
+
+    def equilibrium_adjoint(self, prim, g):
+        assert prim.shape == (4, 1, 1, 1) and g.shape == (10, 1, 1, 1)
+        return torch.full((4, 1, 1, 1), float(g[0, 0, 0, 0]), dtype=prim.dtype)
 
     # reverse
     def new_costate(self):
@@ -79,3 +91,22 @@ def test_reverse_steps_visit_every_state_once(sweeps, T, K):
     assert sim.reverse == list(range(T - 1, -1, -1))
     assert float(M0.grad[0, 0, 0, 0]) == T          # one co-state update per step
     assert float(tau.grad) == T                     # one sensitivity term per step
+
+
+@pytest.mark.parametrize("sweeps", [False, True])
+@pytest.mark.parametrize("T,K", [(1, 1), (7, 3), (8, 4)])
+def test_rollout_from_primitive_fields(sweeps, T, K):
+    """MomentLBRollout.apply(rho, u0, tau, sim, n, K): the same schedule,
+    with the co-state of M0 handed to the transpose of the equilibrium map
+    and split into the gradients of rho and u0."""
+    sim = FakeSim(sweeps)
+    rho = torch.zeros((1, 1, 1), dtype=torch.float64, requires_grad=True)
+    u0 = torch.zeros((3, 1, 1, 1), dtype=torch.float64, requires_grad=True)
+    tau = torch.tensor(0.8, dtype=torch.float64, requires_grad=True)
+    MT = AG.MomentLBRollout.apply(rho, u0, tau, sim, T, K)
+    assert float(MT[0, 0, 0, 0]) == T
+    MT.sum().backward()
+    assert sim.reverse == list(range(T - 1, -1, -1))
+    assert rho.grad.shape == rho.shape and u0.grad.shape == u0.shape
+    assert float(rho.grad.flatten()[0]) == T and torch.all(u0.grad == T)
+    assert float(tau.grad) == T
