@@ -324,6 +324,25 @@ int lbm_adjoint_step(lbm_ctx *ctx, const lbm_fields *state_t, const lbm_fields *
 int lbm_adjoint_step_stored(lbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out,
                             double *dtau_accum);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * reverse step as lbm_adjoint_step_stored, same arguments and results bit for
+ * bit, calling no hipMalloc, hipFree or allocating library routine.  The
+ * two-species step keeps the co-state of the colour gradient (3 N reals, in
+ * the blocked layout) in a static device array of 64 MiB instead of the
+ * context's lazily allocated buffer; each device the library runs on holds
+ * that array from the first lbm_create on it until the process ends.  Every
+ * call on one device shares its array: calls that overlap on one device (on
+ * different streams or host threads) race, and must be ordered by the
+ * caller.  The array is written in full before it is read within each call,
+ * so nothing carries over between calls.  One species needs no scratch.
+ * Errors: LBM_EINVAL (NULL or aliased buffers, or a two-species box whose
+ * colour-gradient co-state exceeds 64 MiB: above about 5.6 M nodes in FP32,
+ * 2.8 M in FP64, e.g. 128^3 fits both), LBM_ESTATE (as lbm_adjoint_step_stored),
+ * LBM_EDEVICE. */
+int lbm_adjoint_step_stored_noalloc(lbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out,
+                                    double *dtau_accum);
+
 /* Two reverse steps in one pass, co-states in the stored layout:
  * lam_out = J(state_t0)^T J(state_t1)^T lam_next, where state_t1 is the state
  * one step after state_t0 (both in the format of lbm_save_state), i.e. the

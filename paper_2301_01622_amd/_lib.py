@@ -97,6 +97,7 @@ def load() -> ctypes.CDLL:
         "lbm_equilibrium_moments_adjoint": (c_int, [c_void, P(Fields), P(Fields), P(Fields)]),
         "lbm_state_bytes_for": (c_int, [Grid, c_int, c_int, P(Opts), P(ctypes.c_int64)]),
         "lbm_adjoint_step_stored": (c_int, [c_void, c_void, c_void, c_void, c_void]),
+        "lbm_adjoint_step_stored_noalloc": (c_int, [c_void, c_void, c_void, c_void, c_void]),
         "lbm_costate_bytes": (c_int, [c_void, P(ctypes.c_int64)]),
         "lbm_costate_to_stored": (c_int, [c_void, c_void, c_void]),
         "lbm_costate_from_stored": (c_int, [c_void, c_void, c_void]),

@@ -6,12 +6,42 @@
 
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <new>
 #include <string>
 
 #include "internal.hpp"
 
+// Static device scratch of lbm_adjoint_step_stored_noalloc: the co-state of
+// the colour gradient of the two-species reverse step (3 fields in the
+// blocked layout, FP32 or FP64).  Every device the library runs on holds its
+// own copy until the process ends.  In host code the name is only a handle
+// for hipGetSymbolAddress; kernels receive the device address resolved once
+// per device at context creation (scratch_ptr).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `dev` (the current device), resolved on the
+// first call for that device.  Returns hipSuccess and sets *ptr.
+hipError_t scratch_ptr(int dev, void **ptr)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 int fail(const lbm_ctx *c, int code, const std::string &msg)
 {
@@ -285,6 +315,13 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
         return LBM_EDEVICE;
     }
     DeviceGuard g(c->device);
+    // The static scratch of the allocation-free entry point, once per device.
+    void *sp = nullptr;
+    if (scratch_ptr(c->device, &sp) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return LBM_EDEVICE;
+    }
     const size_t bytes = c->elem * (size_t)c->state_elems;
     const int copies = plan.copies;  // in place: one copy
     c->owns_state = !external;
@@ -655,15 +692,16 @@ int lbm_adjoint_step2_stored(lbm_ctx *c, const void *state_t1, const void *state
 
 static size_t real_bytes(const lbm_ctx *c) { return c->storage == LBM_STORE_F64 ? 8 : 4; }
 
-// Validation shared by the adjoint entry points, and the colour-gradient
-// co-state buffer the two-species adjoint needs (allocated on first use).
-static int adjoint_ready(lbm_ctx *c)
+// Validation shared by the adjoint entry points, and (if allocate) the
+// colour-gradient co-state buffer the two-species adjoint needs, allocated on
+// first use.
+static int adjoint_ready(lbm_ctx *c, bool allocate = true)
 {
     if (c->scheme != LBM_SCHEME_MOMENT) return fail(c, LBM_ESTATE, "adjoint_step: moment scheme only");
     if (c->species == 2 && c->storage != LBM_STORE_F32 && c->storage != LBM_STORE_F64)
         return fail(c, LBM_ESTATE, "adjoint_step: two species need FP32 or FP64 storage");
     if (c->nc_A != 0.0) return fail(c, LBM_ESTATE, "adjoint_step: not with the near-contact force");
-    if (c->species == 2 && !c->scratch_adj) {
+    if (allocate && c->species == 2 && !c->scratch_adj) {
         if (hipMalloc(&c->scratch_adj, c->elem * (size_t)(c->lay3.plane * c->nz)) != hipSuccess) {
             c->scratch_adj = nullptr;
             (void)hipGetLastError();
@@ -741,6 +779,33 @@ int lbm_adjoint_step_stored(lbm_ctx *c, const void *state, const void *lam_next,
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
     return LBM_OK;
 }
+int lbm_adjoint_step_stored_noalloc(lbm_ctx *c, const void *state, const void *lam_next, void *lam_out,
+                                    double *dtau_accum)
+{
+    if (!c) return LBM_EINVAL;
+    if (!state || !lam_next || !lam_out || lam_next == lam_out)
+        return fail(c, LBM_EINVAL, "adjoint_step_stored_noalloc: NULL or aliased buffers");
+    c->err.clear();
+    int rc = adjoint_ready(c, false);
+    if (rc) return rc;
+    DeviceGuard g(c->device);
+    hipError_t e;
+    if (c->species == 2) {
+        const size_t need = c->elem * (size_t)(c->lay3.plane * c->nz);
+        if (need > kScratchBytes)
+            return fail(c, LBM_EINVAL,
+                        "adjoint_step_stored_noalloc: the colour-gradient co-state needs " + std::to_string(need) +
+                            " bytes, beyond the static scratch of " + std::to_string(kScratchBytes) + " bytes");
+        void *sp = nullptr;
+        if ((e = scratch_ptr(c->device, &sp)) != hipSuccess) return hip_fail(c, e, "adjoint_step_stored_noalloc");
+        e = lbm::launch_cg_adjoint_step(c, state, lam_next, lam_out, dtau_accum, true, sp);
+    } else {
+        e = lbm::launch_adjoint_step(c, state, lam_next, lam_out, dtau_accum, true);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint_step_stored_noalloc");
+    return LBM_OK;
+}
+
 int lbm_costate_bytes(const lbm_ctx *c, int64_t *bytes)
 {
     if (!c || !bytes) return LBM_EINVAL;

@@ -495,7 +495,7 @@ __global__ __launch_bounds__(256) void k_cg_add_partials(const double *__restric
 }
 
 template <int Q, class R, int TX, int TY, bool LSTORED>
-hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out, double *dtau)
+hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out, double *dtau, void *gG_buf)
 {
     TileGrid g;
     g.nx = c->nx;
@@ -509,7 +509,7 @@ hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *la
     g.chunks = (c->nz + g.zchunk - 1) / g.zchunk;
     const int64_t blocks = (int64_t)g.tiles_x * g.tiles_y * g.chunks;
     if (blocks > 5 * kReduceBlocks) return hipErrorInvalidConfiguration;
-    R *gG = static_cast<R *>(c->scratch_adj);
+    R *gG = static_cast<R *>(gG_buf);
     hipLaunchKernelGGL((k_cg_adjoint_tile<Q, R, TX, TY, LSTORED>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
                        static_cast<const R *>(state), static_cast<const R *>(lam_in), static_cast<R *>(lam_out), gG,
                        g, c->lay3, (R)c->omega, (R)(c->A / 9.0), (R)c->beta, c->tau, c->partials);
@@ -531,25 +531,26 @@ hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *la
 }
 
 template <bool LS>
-hipError_t dispatch(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out, double *dtau)
+hipError_t dispatch(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out, double *dtau, void *gG)
 {
     if (c->storage == LBM_STORE_F32)
-        return c->q == 19 ? run<19, float, 64, 4, LS>(c, state, lam_in, lam_out, dtau)
-                          : run<27, float, 32, 8, LS>(c, state, lam_in, lam_out, dtau);
+        return c->q == 19 ? run<19, float, 64, 4, LS>(c, state, lam_in, lam_out, dtau, gG)
+                          : run<27, float, 32, 8, LS>(c, state, lam_in, lam_out, dtau, gG);
     if (c->storage == LBM_STORE_F64)
-        return c->q == 19 ? run<19, double, 32, 8, LS>(c, state, lam_in, lam_out, dtau)
-                          : run<27, double, 32, 8, LS>(c, state, lam_in, lam_out, dtau);
+        return c->q == 19 ? run<19, double, 32, 8, LS>(c, state, lam_in, lam_out, dtau, gG)
+                          : run<27, double, 32, 8, LS>(c, state, lam_in, lam_out, dtau, gG);
     return hipErrorNotSupported;
 }
 
 } // namespace
 
 hipError_t launch_cg_adjoint_step(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out,
-                                  double *dtau_accum, bool stored)
+                                  double *dtau_accum, bool stored, void *gG_scratch)
 {
-    if (c->species != 2 || !c->scratch_adj) return hipErrorNotSupported;
-    return stored ? dispatch<true>(c, state, lam_in, lam_out, dtau_accum)
-                  : dispatch<false>(c, state, lam_in, lam_out, dtau_accum);
+    if (!gG_scratch) gG_scratch = c->scratch_adj;
+    if (c->species != 2 || !gG_scratch) return hipErrorNotSupported;
+    return stored ? dispatch<true>(c, state, lam_in, lam_out, dtau_accum, gG_scratch)
+                  : dispatch<false>(c, state, lam_in, lam_out, dtau_accum, gG_scratch);
 }
 
 } // namespace lbm

@@ -74,11 +74,12 @@ hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out, bool phi_
 hipError_t launch_adjoint_step(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out,
                                double *dtau_accum, bool stored);
 
-// Discrete adjoint of the two-species (colour-gradient) moment step; uses
-// c->scratch_adj (3 fields in the blocked layout lay3) for the co-state of
-// the colour gradient.
+// Discrete adjoint of the two-species (colour-gradient) moment step; keeps
+// the co-state of the colour gradient (3 fields in the blocked layout lay3,
+// written in full before it is read) in gG_scratch, or in c->scratch_adj if
+// that is NULL.
 hipError_t launch_cg_adjoint_step(const lbm_ctx *c, const void *state, const void *lam_in, void *lam_out,
-                                  double *dtau_accum, bool stored);
+                                  double *dtau_accum, bool stored, void *gG_scratch = nullptr);
 
 // Co-state between the public layout (nfields fields, field k at
 // base + k*stride, elements of pub_dtype; stride <= 0: N, pub_dtype < 0: the
