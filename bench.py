@@ -92,6 +92,11 @@ def time_steps(sim, stream, steps: int, warmup: int, repeats: int = 3) -> dict:
     return {"ms": statistics.median(kern), "e2e_ms": statistics.median(e2e), "repeats": [round(v, 5) for v in kern]}
 
 
+def _log(msg: str) -> None:
+    """Progress of the legs on stderr (the JSON line goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _rate(N: int, ms: float) -> float:
     return round(N / (ms * 1e-3) / 1e6, 1)
 
@@ -286,6 +291,13 @@ def two_component(steps: int, warmup: int, repeats: int):
         pms = ptm["ms"]
         p_state, p_step = ps.memory_info()
         ps.close()
+        # The paper's split schedule of the same step: phase-field, collision
+        # and streaming passes (same results, more bytes moved).
+        sp = LBM((512, 256, 256), 19, 0.8, species=2, storage="f32", sigma=0.01, beta=0.7, split=True, stream=stream)
+        sp.set_equilibrium(prim, uu)
+        stm = time_steps(sp, stream, steps, warmup, repeats)["ms"]
+        _, sp_step = sp.memory_info()
+        sp.close()
         # The same collision with the near-contact force (A_h = 0.01, 4 probes).
         nc = {}
         for scheme in ("moment", "population"):
@@ -315,6 +327,15 @@ def two_component(steps: int, warmup: int, repeats: int):
             "bytes_per_node_state": p_state // N,
         },
         "speedup_vs_population_lb": round(pms / ms, 3),
+        "split_approach": {
+            "scheme": "moment LB as the split approach (phase-field, collision and streaming passes)",
+            "value": _rate(N, stm),
+            "unit": "MLUPS",
+            "ms_per_step": round(stm, 5),
+            "bytes_per_node_step": sp_step // N,
+            "hbm_frac": round(sp_step / (stm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "fused_speedup": round(stm / ms, 3),
+        },
         "near_contact": {"A_h": 0.01, "h_max": 4, **nc},
         "adjoint": adjoint,
     }
@@ -408,6 +429,7 @@ def main() -> int:
 
     with torch.cuda.stream(stream):
         spl = args.steps_per_sweep
+        _log(f"headline: {n}^3 D3Q27 FP32, {args.steps} steps x {reps}")
         sim, sim_mem = _create(LBM, (n, n, n), q, tau, storage="f32", stream=stream, steps_per_sweep=spl)
         sim.set_equilibrium(rho_d, u_d)
         warm_ms = gpu_warmup(sim, args.gpu_warmup_ms)
@@ -416,6 +438,7 @@ def main() -> int:
         ms = head["ms"]
         state_bytes, step_bytes = sim.memory_info()
 
+        _log("one step per launch, adjoint, copy, split, population legs")
         # One step per launch, for comparison with the two-step sweeps.
         s1 = LBM((n, n, n), q, tau, storage="f32", stream=stream, steps_per_sweep=1)
         s1.set_equilibrium(rho_d, u_d)
@@ -497,16 +520,19 @@ def main() -> int:
 
     two = None
     if not args.no_two_component:
+        _log("two-component 512x256x256 legs")
         two = two_component(side, args.warmup, reps)
 
     paper = None
     if not args.no_paper_workload:
+        _log("paper workload 128^3")
         paper = paper_workload(side, args.warmup, reps)
 
     # Reduced-precision storage on 512^3 D3Q27 (tau = 0.55, shear wave plus
     # solenoidal noise): FP16 and BF16 moments, FP32 arithmetic.
     reduced = None
     if not args.no_reduced_precision:
+        _log("reduced-precision 512^3 legs")
         reduced = {"workload": "512^3 periodic box, D3Q27, tau=0.55, u_x = 0.01 sin(2 pi y/512) + solenoidal noise "
                                "1e-4 (seed 16220004), 16-bit moments (rho-1, j, S scaled), FP32 arithmetic"}
         rho5, u5 = inputs.shear_wave_with_noise(512, seed=inputs.SEED_C4, u0=0.01, noise=1e-4)
@@ -610,6 +636,7 @@ def main() -> int:
         line["speedup_vs_population_lb"] = round(mlups / pop["value"], 3)
         line["speedup_vs_population_lb_in_place"] = round(mlups / pop["in_place"]["value"], 3)
     if not args.no_cpu_baseline:
+        _log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(n, q, tau, args.cpu_steps, rho, u)
     print(json.dumps(line), flush=True)
     return 0

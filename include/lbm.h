@@ -101,10 +101,15 @@ typedef struct {
     int split;       /* 0 (default): fused step, one kernel.  1: the paper's split approach
                         (Sec. III.A), for comparison: a collision pass relaxes the stored moments
                         in place (rho, j, S) -> (rho, j, S'), then the streaming pass
-                        reconstructs, pulls and sums.  Moment scheme, one species only
-                        (else LBM_EINVAL); results equal the fused step's bit for bit with
-                        FP32/FP64 storage (16-bit storage rounds the stored S'); 36 instead of
-                        20 stored values moved per node; lbm_step_state gives LBM_ESTATE */
+                        reconstructs, pulls and sums; two species add a phase-field pass
+                        before the collision pass, which also applies the perturbation (and
+                        the near-contact force) and writes the interface normal for the
+                        streaming pass's recolouring (scratch of 4 N reals).  Moment scheme
+                        only (else LBM_EINVAL); results equal the fused step's bit for bit
+                        with FP32/FP64 storage (16-bit storage rounds the stored S'); stored
+                        values moved per node: 36 instead of 20 (one species), 49 (52 with
+                        the near-contact force) instead of 22 (two species); lbm_step_state
+                        gives LBM_ESTATE */
     int steps_per_sweep; /* time steps lbm_step applies per pass over the state: 1, or 2 (two
                         steps carried through each tile in one pass, the state read and written
                         once per two steps; results equal single steps bit for bit).  2 needs

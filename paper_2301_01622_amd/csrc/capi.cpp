@@ -222,7 +222,7 @@ static int validate(lbm_grid grid, int lattice, int species, const lbm_opts &o, 
     if (species != 1 && species != 2) return LBM_EINVAL;
     if (o.scheme != LBM_SCHEME_MOMENT && o.scheme != LBM_SCHEME_POPULATION && o.scheme != LBM_SCHEME_POPULATION_AA)
         return LBM_EINVAL;
-    if (o.split != 0 && (o.split != 1 || o.scheme != LBM_SCHEME_MOMENT || species != 1)) return LBM_EINVAL;
+    if (o.split != 0 && (o.split != 1 || o.scheme != LBM_SCHEME_MOMENT)) return LBM_EINVAL;
     if (o.scheme == LBM_SCHEME_POPULATION_AA &&
         (species != 1 || (o.storage != LBM_STORE_F32 && o.storage != LBM_STORE_F64)))
         return LBM_EINVAL;
@@ -341,10 +341,23 @@ int lbm_create(lbm_ctx **out, lbm_grid grid, int lattice, double tau, int specie
         lbm_destroy(c);
         return LBM_ENOMEM;
     }
-    // Near-contact force (3 N) and, for the moment scheme, its phase field (N).
-    if (c->nc_A != 0.0 &&
-        hipMalloc(&c->scratch_nc, c->elem * (size_t)c->N * (c->scheme == LBM_SCHEME_MOMENT ? 4 : 3)) != hipSuccess) {
-        c->scratch_nc = nullptr;
+    // Near-contact force (3 N), for the moment scheme its phase field (N), and
+    // two bytes per force block; zeroed (the force passes rewrite only blocks
+    // whose flags say they may hold non-zero values).
+    if (c->nc_A != 0.0) {
+        if (hipMalloc(&c->scratch_nc, lbm::nc_scratch_bytes(c)) != hipSuccess) {
+            c->scratch_nc = nullptr;
+            lbm_destroy(c);
+            return LBM_ENOMEM;
+        }
+        if (hipMemsetAsync(c->scratch_nc, 0, lbm::nc_scratch_bytes(c), c->stream) != hipSuccess) {
+            lbm_destroy(c);
+            return LBM_EDEVICE;
+        }
+    }
+    // Split two-species step: phase field (N) and interface normal (3 N).
+    if (c->split && species == 2 && hipMalloc(&c->scratch_split, c->elem * 4 * (size_t)c->N) != hipSuccess) {
+        c->scratch_split = nullptr;
         lbm_destroy(c);
         return LBM_ENOMEM;
     }
@@ -508,7 +521,10 @@ int lbm_step(lbm_ctx *c, int n)
         } else {
             const void *in = c->state[c->cur];
             void *out = c->state[1 - c->cur];
-            if (c->split) {
+            if (c->split && c->species == 2) {
+                // Split approach: phase field, collision in place, streaming.
+                e = lbm::launch_cg_split_step(c, c->state[c->cur], out);
+            } else if (c->split) {
                 // Split approach: relax the current state in place, then stream.
                 e = lbm::launch_moment_collide(c, c->state[c->cur]);
                 if (e == hipSuccess) e = lbm::launch_moment_step(c, in, out, true);
@@ -542,11 +558,18 @@ int lbm_memory_info(const lbm_ctx *c, int64_t *state_bytes, int64_t *step_bytes)
     const int64_t copies = c->scheme == LBM_SCHEME_POPULATION_AA ? 1 : 2;
     if (state_bytes)
         *state_bytes = copies * per_copy + (c->scratch_phi ? (int64_t)sizeof(float) * c->N : 0) +
-                       (c->scratch_nc ? (int64_t)c->elem * c->N * (c->scheme == LBM_SCHEME_MOMENT ? 4 : 3) : 0) +
-                       (c->scratch_adj ? (int64_t)c->elem * c->lay3.plane * c->nz : 0);
-    // Split approach: the collision pass reads all stored fields and writes S'
-    // (6 fields), the streaming pass reads and writes all of them.
-    const int64_t moved = c->split ? 3 * (int64_t)c->nfields + 6 : 2 * (int64_t)c->nfields;
+                       (c->scratch_nc ? (int64_t)lbm::nc_scratch_bytes(c) : 0) +
+                       (c->scratch_adj ? (int64_t)c->elem * c->lay3.plane * c->nz : 0) +
+                       (c->scratch_split ? (int64_t)c->elem * 4 * c->N : 0);
+    // Split approach, one species: the collision pass reads all stored fields
+    // and writes S' (6 fields), the streaming pass reads and writes all of
+    // them.  Two species: the phase pass reads dr and rho1 and writes phi (3),
+    // the collision pass reads the 11 fields and phi and writes S' and n (21,
+    // 24 with a force, which also rewrites j), the streaming pass reads the
+    // 11 fields and n and writes 11 (25).
+    const int64_t moved = !c->split ? 2 * (int64_t)c->nfields
+                          : c->species == 1 ? 3 * (int64_t)c->nfields + 6
+                                            : (c->nc_A != 0.0 ? 52 : 49);
     if (step_bytes) *step_bytes = moved * (int64_t)c->elem * c->N;
     return LBM_OK;
 }

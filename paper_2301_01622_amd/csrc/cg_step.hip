@@ -22,6 +22,7 @@
 
 #include <type_traits>
 
+#include "cg_math.hpp"
 #include "internal.hpp"
 #include "moment_math.hpp"
 #include "storage.hpp"
@@ -29,35 +30,6 @@
 
 namespace lbm {
 namespace {
-
-// Smoothed gradient norm D = sqrt(|G|^2 + kEpsG^2): n = G/D is the unit
-// normal on every interface and fades smoothly to zero where the gradient
-// vanishes; the perturbation uses the same D.
-constexpr double kEpsG = 1e-3;
-
-template <class R>
-__device__ __forceinline__ R sqrt_(R x)
-{
-    return __builtin_sqrt(x);
-}
-template <>
-__device__ __forceinline__ float sqrt_<float>(float x)
-{
-    return __builtin_sqrtf(x);
-}
-
-// 1/sqrt(x): FP32 uses the hardware reciprocal square root (about 1 ulp);
-// FP64 keeps the correctly rounded quotient.
-template <class R>
-__device__ __forceinline__ R rsqrt_(R x)
-{
-    return R(1) / sqrt_<R>(x);
-}
-template <>
-__device__ __forceinline__ float rsqrt_<float>(float x)
-{
-    return __builtin_amdgcn_rsqf(x);
-}
 
 template <class R>
 struct CgAcc {
@@ -77,16 +49,63 @@ __host__ __device__ constexpr double inv_speed(int cx, int cy, int cz)
                                                                                            : 0.57735026918962576451;
 }
 
+// LDS layout of the published populations.  Slot s (one moving direction
+// c, the own column (0, 0, +-1) excepted; see lds_slot) holds one value per
+// node that can send c into the tile: the tile widened by one node on the
+// side c comes from, i.e. x in [-1, TX) for c_x = 1, [0, TX] for c_x = -1,
+// [0, TX) for c_x = 0, and likewise in y.  Region s is a (TX + |c_x|) x
+// (TY + |c_y|) block, row-major, at offset O(s); a node at source-region
+// coordinates (hx, hy) = (x + 1, y + 1) sits at OFF(s) + hy W(s) + hx with
+// W(s) = TX + |c_x|, so every index is a per-node base (hy TX + hx or
+// hy (TX + 1) + hx) plus a compile-time offset.
+template <int Q, int TX, int TY>
+struct SlotLayout {
+    struct Dir {
+        int cx, cy, cz;
+    };
+    static constexpr Dir dir(int s)
+    {
+        int k = 0;
+        for (int z = -1; z <= 1; ++z)
+            for (int sl = 0; sl < 9; ++sl) {
+                if (sl == 4 || !has_dir<Q>(sl % 3 - 1, sl / 3 - 1, z)) continue;
+                if (k == s) return Dir{sl % 3 - 1, sl / 3 - 1, z};
+                ++k;
+            }
+        return Dir{0, 0, 0};
+    }
+    static constexpr int width(int s) { return TX + (dir(s).cx != 0 ? 1 : 0); }
+    static constexpr int height(int s) { return TY + (dir(s).cy != 0 ? 1 : 0); }
+    static constexpr int start(int s)
+    {
+        int o = 0;
+        for (int k = 0; k < s; ++k) o += width(k) * height(k);
+        return o;
+    }
+    static constexpr int total() { return start(kLdsSlots<Q>); }
+    // OFF(s): start(s) minus the region coordinates of source node (0, 0).
+    static constexpr int off(int s)
+    {
+        return start(s) - (dir(s).cy > 0 ? 0 : 1) * width(s) - (dir(s).cx > 0 ? 0 : 1);
+    }
+};
+
 // FORCE: a body force (three arrays of N values, x fastest) enters the
 // mixture collision with Guo's forcing: u* = (j + F/2)/rho in the
 // equilibrium, (1 - omega/2)(u* F + F u*) added to the collided S, j + F
 // streamed; the phase field phi = 2 rho1/rho - 1 of the stored output is
 // written to phi_out (N values, x fastest) for the next step's force.
-template <int Q, class R, int TX, int TY, bool FORCE>
-__global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R *__restrict__ out, TileGrid g,
+// COLL (split schedule): `in` holds post-collision moments (S' with the
+// perturbation, j + F under a force) and frc the interface normal n (three
+// arrays of N values); the step then only reconstructs, recolours, pulls and
+// sums, with the same arithmetic per node as the fused step.
+template <int Q, class R, int TX, int TY, bool FORCE, int WPE, bool COLL = false>
+__global__ __launch_bounds__(TX *TY, WPE) void k_cg_tile(const R *__restrict__ in, R *__restrict__ out, TileGrid g,
                                                     R omega, R A9, R beta, const R *__restrict__ frc,
                                                     R *__restrict__ phi_out)
 {
+    static_assert(!(FORCE && COLL), "the split schedule applies the force in its collision pass");
+    constexpr bool VEC3 = FORCE || COLL;  // three extra arrays per node (F, or n)
     constexpr int NT = TX * TY;
     constexpr int SX = TX + 2, SY = TY + 2, SN = SX * SY;  // source region (radius 1)
     constexpr int FX = TX + 4, FY = TY + 4, FN = FX * FY;  // phase-field region (radius 2)
@@ -94,8 +113,9 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
     constexpr int OUTER = FN - SN;                         // radius-2 ring (phi only)
     static_assert(RING <= NT && OUTER <= NT, "halo rings must fit one pass");
     constexpr int NS = kLdsSlots<Q>;
-    __shared__ R lds_h[NS * SN];   // shifted mixture populations
-    __shared__ R lds_f[NS * SN];   // species-1 populations
+    using SL = SlotLayout<Q, TX, TY>;
+    __shared__ R lds_h[SL::total()];  // shifted mixture populations
+    __shared__ R lds_f[SL::total()];  // species-1 populations
     __shared__ R lds_phi[3 * FN];  // phase field of three planes
 
     const int b = xcd_tile_id();
@@ -112,17 +132,28 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
     const bool active = (x0 + lx < g.nx) && (y0 + ly < g.ny);
     const int h0 = (ly + 1) * SX + (lx + 1);
 
-    // Radius-1 ring node of this thread (source region coordinates).
-    const bool has_ring = tid < RING;
-    int hr;
-    {
-        const int m = tid;
-        int hx, hy;
-        if (m < SX) { hx = m; hy = 0; }
-        else if (m < 2 * SX) { hx = m - SX; hy = SY - 1; }
-        else if (m < 2 * SX + TY) { hx = 0; hy = 1 + (m - 2 * SX); }
-        else { hx = SX - 1; hy = 1 + (m - 2 * SX - TY); }
-        hr = hy * SX + hx;
+    // Radius-1 ring node of this thread (source region coordinates).  The
+    // ring nodes of the top and bottom rows (x inside the tile) take threads
+    // [0, 2 TX); those of the left and right columns (corners included) take
+    // threads from the next multiple of 64 on, so that every wave holds ring
+    // nodes of one orientation only.  A ring node sends into the tile only
+    // the directions with c_y = d (rows) or c_x = d (columns), d its inward
+    // sign.
+    constexpr int ROWS = 2 * TX, CB = (ROWS + 63) / 64 * 64, COLS = 2 * SY;
+    static_assert(ROWS + COLS == RING && CB + COLS <= NT, "ring threads must fit the workgroup");
+    const bool ring_row = tid < ROWS;
+    const bool ring_col = tid >= CB && tid < CB + COLS;
+    const bool has_ring = ring_row || ring_col;
+    int hr = 0, dsign = 1;
+    if (ring_row) {
+        const bool top = tid < TX;
+        hr = (top ? 0 : SY - 1) * SX + 1 + (top ? tid : tid - TX);
+        dsign = top ? 1 : -1;
+    } else if (ring_col) {
+        const int m = tid - CB;
+        const bool left = m < SY;
+        hr = (left ? m : m - SY) * SX + (left ? 0 : SX - 1);
+        dsign = left ? 1 : -1;
     }
     // Radius-2 ring node of this thread (phase-field region coordinates).
     const bool has_outer = tid < OUTER;
@@ -142,17 +173,24 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
     };
     const int64_t own_xy = xy_src(h0);
     const int64_t ring_xy = has_ring ? xy_src(hr) : 0;
+    const int ring_y = hr / SX - 1;  // tile row of the ring node (-1 .. TY)
     // Offsets of the force arrays (public layout) of the two source nodes.
     auto lin_src = [&](int h) -> int64_t {
         return (int64_t)wrap_coord(x0 - 1 + h % SX, g.nx) + (int64_t)g.nx * wrap_coord(y0 - 1 + h / SX, g.ny);
     };
-    const int64_t own_lin = FORCE ? lin_src(h0) : 0;
-    const int64_t ring_lin = FORCE && has_ring ? lin_src(hr) : 0;
+    const int64_t own_lin = VEC3 ? lin_src(h0) : 0;
+    const int64_t ring_lin = VEC3 && has_ring ? lin_src(hr) : 0;
     const int64_t plane_lin = (int64_t)g.nx * g.ny;
     const int64_t outer_xy =
         has_outer ? g.lay.xy(wrap_coord(x0 - 2 + ko % FX, g.nx), wrap_coord(y0 - 2 + ko / FX, g.ny))
                   : 0;
     const int k_own = src_to_phi(h0), k_ring = src_to_phi(hr);
+    // LDS bases (SlotLayout) of the two source nodes: hy TX + hx and
+    // hy (TX + 1) + hx.
+    auto base_a = [](int h) { return (h / SX) * TX + h % SX; };
+    auto base_b = [](int h) { return (h / SX) * (TX + 1) + h % SX; };
+    const int ba0 = base_a(h0), bb0 = base_b(h0), bar = base_a(hr), bbr = base_b(hr);
+    auto lds_at = [&](int s, int ba, int bb) { return SL::off(s) + (SL::width(s) == TX ? ba : bb); };
 
     using M11 = Moments<R, 11>;
     struct PlaneRegs {
@@ -166,11 +204,11 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
         const int64_t zo = (int64_t)zwrap(p) * plane;
         load_moments<R, 11>(in, kBlock, own_xy + zo, r.own);
         if (has_ring) load_moments<R, 11>(in, kBlock, ring_xy + zo, r.ring);
-        if (has_outer) {
+        if (!COLL && has_outer) {
             r.outer_dr = in[outer_xy + zo];
             r.outer_r1 = in[kBlock + outer_xy + zo];
         }
-        if (FORCE) {
+        if (VEC3) {
             const int64_t zl = (int64_t)zwrap(p) * plane_lin;
             r.fox = frc[own_lin + zl];
             r.foy = frc[g.N + own_lin + zl];
@@ -182,9 +220,10 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
             }
         }
     };
-    auto phi_of = [](R dr, R r1) { return fma_(R(2) * r1, reciprocal<R>(R(1) + dr), R(-1)); };
+    auto phi_of = [](R dr, R r1) { return phase_field<R>(dr, r1); };
     auto slot_of = [&](int p) { return (p - z0 + 2) % 3; };
     auto write_phi = [&](int p, const PlaneRegs &r) {
+        if (COLL) return;
         R *ph = lds_phi + slot_of(p) * FN;
         ph[k_own] = phi_of(r.own.v[0], r.own.v[1]);
         if (has_ring) ph[k_ring] = phi_of(r.ring.v[0], r.ring.v[1]);
@@ -196,91 +235,96 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
     acc[1].zero();
     acc[2].zero();
 
-    // Collides one source node (region slot h) and publishes h~ and f1.
-    auto publish = [&](int p, const M11 &v, int h, R *own_h, R *own_f, R fx, R fy, R fz) {
+    // Post-collision state of one source node (region slot h): the collided
+    // moments with the perturbation, the interface normal n = G/D, rho1/rho
+    // and the recolouring amplitude beta rho1 rho2/rho.
+    struct NodePrep {
+        Collided<R> c;
+        R nx, ny, nz, a, B;
+    };
+    auto prep = [&](int p, const M11 &v, int h, R fx, R fy, R fz) -> NodePrep {
+        if constexpr (COLL) {
+            // Stored post-collision moments and normal (fx, fy, fz = n).
+            NodePrep o;
+            o.c = collided_from<R>(v.v[0], v.v[2], v.v[3], v.v[4], v.v[5], v.v[6], v.v[7], v.v[8], v.v[9], v.v[10]);
+            o.nx = fx;
+            o.ny = fy;
+            o.nz = fz;
+            const R dr = v.v[0], r1 = v.v[1];
+            const R inv_rho = reciprocal<R>(R(1) + dr);
+            o.a = r1 * inv_rho;
+            o.B = beta * (o.a * (R(1) + dr - r1));
+            return o;
+        }
         const int kc = src_to_phi(h);
         const R *phm = lds_phi + slot_of(p - 1) * FN;
         const R *ph0 = lds_phi + slot_of(p) * FN;
         const R *php = lds_phi + slot_of(p + 1) * FN;
-        // G = 3 sum_i w_i c_i phi(y + c_i): the signed phi values are summed
-        // per weight class (faces, edges, corners) and scaled once per class.
-        R gf[3] = {R(0), R(0), R(0)}, ge[3] = {R(0), R(0), R(0)}, gc[3] = {R(0), R(0), R(0)};
-#pragma unroll
-        for (int cz = -1; cz <= 1; ++cz)
-#pragma unroll
-            for (int cy = -1; cy <= 1; ++cy)
-#pragma unroll
-                for (int cx = -1; cx <= 1; ++cx) {
-                    if ((cx == 0 && cy == 0 && cz == 0) || !has_dir<Q>(cx, cy, cz)) continue;
-                    const R *ph = cz < 0 ? phm : (cz == 0 ? ph0 : php);
-                    const R f = ph[kc + cy * FX + cx];
-                    const int cls = cx * cx + cy * cy + cz * cz;
-                    R *acc_c = cls == 1 ? gf : (cls == 2 ? ge : gc);
-                    if (cx != 0) acc_c[0] = cx > 0 ? acc_c[0] + f : acc_c[0] - f;
-                    if (cy != 0) acc_c[1] = cy > 0 ? acc_c[1] + f : acc_c[1] - f;
-                    if (cz != 0) acc_c[2] = cz > 0 ? acc_c[2] + f : acc_c[2] - f;
-                }
-        constexpr double w3f = 3.0 * weight<Q>(1, 0, 0), w3e = 3.0 * weight<Q>(1, 1, 0), w3c = 3.0 * weight<Q>(1, 1, 1);
-        R Gv[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            Gv[a] = fma_(R(w3e), ge[a], R(w3f) * gf[a]);
-            if (Q == 27) Gv[a] = fma_(R(w3c), gc[a], Gv[a]);
-        }
-        const R Gx = Gv[0], Gy = Gv[1], Gz = Gv[2];
-        const R G2 = fma_(Gx, Gx, fma_(Gy, Gy, Gz * Gz));
-        const R invD = rsqrt_<R>(G2 + R(kEpsG * kEpsG));
-        const R nx = Gx * invD, ny = Gy * invD, nz = Gz * invD;
-
+        R G[3];
+        colour_gradient<Q, R>(
+            [&](int cx, int cy, int cz) { return (cz < 0 ? phm : (cz == 0 ? ph0 : php))[kc + cy * FX + cx]; }, G);
+        const CgCollided<R> cc = cg_collide<R, FORCE>(v.v, G, omega, A9, fx, fy, fz);
+        NodePrep o;
+        o.c = cc.c;
+        o.nx = cc.nx;
+        o.ny = cc.ny;
+        o.nz = cc.nz;
         const R dr = v.v[0], r1 = v.v[1];
-        Collided<R> c;
-        if (FORCE) {
-            // Guo's forcing: equilibrium at j* = j + F/2, source (1 - omega/2)(u* F + F u*).
-            const R jsx = fma_(R(0.5), fx, v.v[2]), jsy = fma_(R(0.5), fy, v.v[3]), jsz = fma_(R(0.5), fz, v.v[4]);
-            c = collide<R>(dr, jsx, jsy, jsz, v.v[5], v.v[6], v.v[7], v.v[8], v.v[9], v.v[10], omega);
-            const R k = (R(1) - R(0.5) * omega) * reciprocal<R>(R(1) + dr);
-            const R kx = k * jsx, ky = k * jsy, kz = k * jsz;
-            c.sxx = fma_(R(2) * kx, fx, c.sxx);
-            c.syy = fma_(R(2) * ky, fy, c.syy);
-            c.szz = fma_(R(2) * kz, fz, c.szz);
-            c.sxy = fma_(kx, fy, fma_(ky, fx, c.sxy));
-            c.sxz = fma_(kx, fz, fma_(kz, fx, c.sxz));
-            c.syz = fma_(ky, fz, fma_(kz, fy, c.syz));
-            c.jx = v.v[2] + fx;
-            c.jy = v.v[3] + fy;
-            c.jz = v.v[4] + fz;
-        } else {
-            c = collide<R>(dr, v.v[2], v.v[3], v.v[4], v.v[5], v.v[6], v.v[7], v.v[8], v.v[9], v.v[10], omega);
-        }
-        // Perturbation: A/9 (G G - |G|^2 I)/D.
-        const R a9 = A9 * invD;
-        c.sxx = fma_(a9, fma_(Gx, Gx, -G2), c.sxx);
-        c.syy = fma_(a9, fma_(Gy, Gy, -G2), c.syy);
-        c.szz = fma_(a9, fma_(Gz, Gz, -G2), c.szz);
-        c.sxy = fma_(a9, Gx * Gy, c.sxy);
-        c.sxz = fma_(a9, Gx * Gz, c.sxz);
-        c.syz = fma_(a9, Gy * Gz, c.syz);
-        // The trace of the perturbation is -2A|G|/9; T follows the collided S'.
-        c.T = fma_(R(-1.5), (c.sxx + c.syy) + c.szz, dr);
-
         const R inv_rho = reciprocal<R>(R(1) + dr);
-        const R a = r1 * inv_rho;                             // rho1/rho
-        const R B = beta * (a * (R(1) + dr - r1));            // beta rho1 rho2/rho
+        o.a = r1 * inv_rho;                             // rho1/rho
+        o.B = beta * (o.a * (R(1) + dr - r1));          // beta rho1 rho2/rho
+        return o;
+    };
+
+    // c.n for a direction given at compile time, from the in-plane sums
+    // n_a +- n_b (formed once per node); the same expression for a direction
+    // wherever the node sits in the tile, so results do not depend on the
+    // tiling.
+    struct NSums {
+        R nx, ny, nz, sxy, dxy, sxz, dxz, syz, dyz;
+    };
+    auto nsums = [](const NodePrep &o) {
+        return NSums{o.nx, o.ny, o.nz, o.nx + o.ny, o.nx - o.ny, o.nx + o.nz, o.nx - o.nz, o.ny + o.nz, o.ny - o.nz};
+    };
+    auto c_dot_n = [](const NSums &n, int cx, int cy, int cz) -> R {
+        const int cls = cx * cx + cy * cy + cz * cz;
+        if (cls == 1) return cx ? (cx > 0 ? n.nx : -n.nx) : cy ? (cy > 0 ? n.ny : -n.ny) : (cz > 0 ? n.nz : -n.nz);
+        if (cls == 2) {
+            if (cz == 0) return cx == cy ? (cx > 0 ? n.sxy : -n.sxy) : (cx > 0 ? n.dxy : -n.dxy);
+            if (cy == 0) return cx == cz ? (cx > 0 ? n.sxz : -n.sxz) : (cx > 0 ? n.dxz : -n.dxz);
+            return cy == cz ? (cy > 0 ? n.syz : -n.syz) : (cy > 0 ? n.dyz : -n.dyz);
+        }
+        const R t = cy == cx ? n.sxy : n.dxy;  // cx nx + cy ny, up to the sign of cx
+        const R txy = cx > 0 ? t : -t;
+        return cz > 0 ? txy + n.nz : txy - n.nz;
+    };
+    // f1_i = (rho1/rho) (w_i + h~_i) + B w_i (c_i.n)/|c_i|, written as
+    // fma(B w_i/|c_i|, c_i.n, fma(rho1/rho, h~_i, (rho1/rho) w_i)) with the
+    // per-class products formed once.
+    struct F1Coef {
+        R a, aw[3], bw[3];
+    };
+    auto f1coef = [](const NodePrep &o) {
+        constexpr double wf = weight<Q>(1, 0, 0), we = weight<Q>(1, 1, 0), wc = weight<Q>(1, 1, 1);
+        return F1Coef{o.a,
+                      {o.a * R(wf), o.a * R(we), o.a * R(wc)},
+                      {o.B * R(wf), o.B * R(we * inv_speed<Q>(1, 1, 0)), o.B * R(wc * inv_speed<Q>(1, 1, 1))}};
+    };
+
+    // Interior node: publishes h~ and f1 of every moving direction (the own
+    // column (0, 0, +-1) and the rest population stay in registers).
+    auto publish = [&](int p, const M11 &v, int h, R *own_h, R *own_f, R fx, R fy, R fz) {
+        const NodePrep o = prep(p, v, h, fx, fy, fz);
         Layer<R> L[3];
-        reconstruct_layer<Q, -1, R>(c, L[0]);
-        reconstruct_layer<Q, 0, R>(c, L[1]);
-        reconstruct_layer<Q, 1, R>(c, L[2]);
+        reconstruct_layer<Q, -1, R>(o.c, L[0]);
+        reconstruct_layer<Q, 0, R>(o.c, L[1]);
+        reconstruct_layer<Q, 1, R>(o.c, L[2]);
+        const NSums ns = nsums(o);
+        const F1Coef k = f1coef(o);
         // Moving directions; the rest population takes what is left of rho1,
         // so that each node emits exactly its species-1 mass (the identity
         // sum_i f1_i = rho1 holds in exact arithmetic: the weights sum to one
         // and the recolouring terms cancel in +-c pairs).
-        // f1_i = (rho1/rho) (w_i + h~_i) + B w_i (c_i.n)/|c_i|, written as
-        // fma(B w_i/|c_i|, c_i.n, fma(rho1/rho, h~_i, (rho1/rho) w_i)) with the
-        // per-class products and the in-plane sums n_a +- n_b formed once.
-        constexpr double wf = weight<Q>(1, 0, 0), we = weight<Q>(1, 1, 0), wc = weight<Q>(1, 1, 1);
-        const R awf = a * R(wf), awe = a * R(we), awc = a * R(wc);
-        const R bwf = B * R(wf), bwe = B * R(we * inv_speed<Q>(1, 1, 0)), bwc = B * R(wc * inv_speed<Q>(1, 1, 1));
-        const R sxy = nx + ny, dxy = nx - ny, sxz = nx + nz, dxz = nx - nz, syz = ny + nz, dyz = ny - nz;
         R f1_moving = R(0);
 #pragma unroll
         for (int cz = -1; cz <= 1; ++cz)
@@ -290,38 +334,57 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
                 if (!has_dir<Q>(cx, cy, cz) || (cx == 0 && cy == 0 && cz == 0)) continue;
                 const R hv = L[cz + 1].v[sl];
                 const int cls = cx * cx + cy * cy + cz * cz;
-                R cn;
-                if (cls == 1) {
-                    cn = cx ? (cx > 0 ? nx : -nx) : cy ? (cy > 0 ? ny : -ny) : (cz > 0 ? nz : -nz);
-                } else if (cls == 2) {
-                    if (cz == 0) cn = cx == cy ? (cx > 0 ? sxy : -sxy) : (cx > 0 ? dxy : -dxy);
-                    else if (cy == 0) cn = cx == cz ? (cx > 0 ? sxz : -sxz) : (cx > 0 ? dxz : -dxz);
-                    else cn = cy == cz ? (cy > 0 ? syz : -syz) : (cy > 0 ? dyz : -dyz);
-                } else {
-                    const R t = cy == cx ? sxy : dxy;  // cx nx + cy ny, up to the sign of cx
-                    const R txy = cx > 0 ? t : -t;
-                    cn = cz > 0 ? txy + nz : txy - nz;
-                }
-                const R aw = cls == 1 ? awf : (cls == 2 ? awe : awc);
-                const R bw = cls == 1 ? bwf : (cls == 2 ? bwe : bwc);
-                const R f1 = fma_(bw, cn, fma_(a, hv, aw));
+                const R f1 = fma_(k.bw[cls - 1], c_dot_n(ns, cx, cy, cz), fma_(k.a, hv, k.aw[cls - 1]));
                 f1_moving += f1;
                 const int s = lds_slot<Q>(cz, sl);
                 if (s >= 0) {
-                    lds_h[s * SN + h] = hv;
-                    lds_f[s * SN + h] = f1;
-                } else if (own_h) {  // own column (0, 0, +-1)
+                    lds_h[lds_at(s, ba0, bb0)] = hv;
+                    lds_f[lds_at(s, ba0, bb0)] = f1;
+                } else {  // own column (0, 0, +-1)
                     own_h[cz + 1] = hv;
                     own_f[cz + 1] = f1;
                 }
             }
-        if (own_h) {
-            own_h[1] = L[1].v[4];
-            own_f[1] = r1 - f1_moving;
-        }
+        own_h[1] = L[1].v[4];
+        own_f[1] = v.v[1] - f1_moving;
     };
 
-    auto pull_layer = [&](auto czc, R oh, R of) {
+    // Ring node with inward sign D across a ring row (ROW: directions
+    // (t, D, cz)) or a ring column (directions (D, t, cz)): publishes only
+    // those, with the interior's arithmetic for each direction.
+    auto publish_ring = [&](auto rowc, auto dc, int p, const M11 &v, int h, R fx, R fy, R fz) {
+        constexpr bool ROW = decltype(rowc)::value;
+        constexpr int D = decltype(dc)::value;
+        const NodePrep o = prep(p, v, h, fx, fy, fz);
+        Layer<R> L[3];
+        reconstruct_layer<Q, -1, R>(o.c, L[0]);
+        reconstruct_layer<Q, 0, R>(o.c, L[1]);
+        reconstruct_layer<Q, 1, R>(o.c, L[2]);
+        const NSums ns = nsums(o);
+        const F1Coef k = f1coef(o);
+#pragma unroll
+        for (int cz = -1; cz <= 1; ++cz)
+#pragma unroll
+            for (int t = -1; t <= 1; ++t) {
+                const int cx = ROW ? t : D, cy = ROW ? D : t;
+                if (!has_dir<Q>(cx, cy, cz)) continue;
+                const int sl = (cx + 1) + 3 * (cy + 1);
+                const int cls = cx * cx + cy * cy + cz * cz;
+                const R hv = L[cz + 1].v[sl];
+                const R f1 = fma_(k.bw[cls - 1], c_dot_n(ns, cx, cy, cz), fma_(k.a, hv, k.aw[cls - 1]));
+                const int s = lds_slot<Q>(cz, sl);
+                // A corner of a ring column lies outside the regions of the
+                // directions that leave it beside the tile; it skips them.
+                if (!ROW && !(t == 0 ? (ring_y >= 0 && ring_y < TY) : (t > 0 ? ring_y < TY : ring_y >= 0)))
+                    continue;
+                lds_h[lds_at(s, bar, bbr)] = hv;
+                lds_f[lds_at(s, bar, bbr)] = f1;
+            }
+    };
+    using Up = std::integral_constant<int, 1>;
+    using Down = std::integral_constant<int, -1>;
+
+    auto pull_layer = [&](auto czc, CgAcc<R> &ac, R oh, R of) {
         constexpr int CZ = decltype(czc)::value;
         Layer<R> fh;
         R r1 = of;
@@ -331,13 +394,14 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
             if (sl == 4) {
                 fh.v[sl] = oh;
             } else if (lds_slot<Q>(CZ, sl) >= 0) {
-                const int idx = lds_slot<Q>(CZ, sl) * SN + h0 - cy * SX - cx;
+                const int s = lds_slot<Q>(CZ, sl);
+                const int idx = lds_at(s, ba0, bb0) - cy * SL::width(s) - cx;
                 fh.v[sl] = lds_h[idx];
                 r1 += lds_f[idx];
             }
         }
-        accumulate_layer<Q, CZ, R>(acc[CZ + 1].m, fh);
-        acc[CZ + 1].rho1 += r1;
+        accumulate_layer<Q, CZ, R>(ac.m, fh);
+        ac.rho1 += r1;
     };
 
     auto plane_step = [&](int p, PlaneRegs &cur, PlaneRegs &nxt) {
@@ -345,12 +409,18 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
         __syncthreads();
         R oh[3], of[3];
         publish(p, cur.own, h0, oh, of, cur.fox, cur.foy, cur.foz);
-        if (has_ring) publish(p, cur.ring, hr, nullptr, nullptr, cur.frx, cur.fry, cur.frz);
+        if (ring_row) {
+            if (dsign > 0) publish_ring(std::true_type(), Up(), p, cur.ring, hr, cur.frx, cur.fry, cur.frz);
+            else publish_ring(std::true_type(), Down(), p, cur.ring, hr, cur.frx, cur.fry, cur.frz);
+        } else if (ring_col) {
+            if (dsign > 0) publish_ring(std::false_type(), Up(), p, cur.ring, hr, cur.frx, cur.fry, cur.frz);
+            else publish_ring(std::false_type(), Down(), p, cur.ring, hr, cur.frx, cur.fry, cur.frz);
+        }
         __syncthreads();
         if (p + 2 <= z_end + 1) fetch(p + 2, cur);
-        pull_layer(std::integral_constant<int, -1>(), oh[0], of[0]);
-        pull_layer(std::integral_constant<int, 0>(), oh[1], of[1]);
-        pull_layer(std::integral_constant<int, 1>(), oh[2], of[2]);
+        pull_layer(std::integral_constant<int, -1>(), acc[0], oh[0], of[0]);
+        pull_layer(std::integral_constant<int, 0>(), acc[1], oh[1], of[1]);
+        pull_layer(std::integral_constant<int, 1>(), acc[2], oh[2], of[2]);
 
         const int d = p - 1;
         if (d >= z0 && active) {
@@ -387,9 +457,30 @@ __global__ __launch_bounds__(TX *TY) void k_cg_tile(const R *__restrict__ in, R 
     }
 }
 
-template <int Q, class R, int TX, int TY, int WG_PER_CU>
-hipError_t run(const lbm_ctx *c, const void *in, void *out, bool phi_cached)
+// Chunk length along z for `tiles` tiles on `slots` resident workgroups: the
+// number of chunks (1 to 8) that minimises rounds x (planes per chunk + the
+// two planes each chunk starts with), rounds = ceil(tiles x chunks / slots).
+inline int balanced_zchunk(int nz, int tiles, int slots)
 {
+    int best = nz, best_cost = 0;
+    for (int ch = 1; ch <= 8; ++ch) {
+        const int zc = (nz + ch - 1) / ch;
+        if (ch > 1 && zc < 16) break;
+        const int64_t rounds = ((int64_t)tiles * ((nz + zc - 1) / zc) + slots - 1) / slots;
+        const int64_t cost = rounds * (zc + 2);
+        if (ch == 1 || cost < best_cost) {
+            best = zc;
+            best_cost = (int)cost;
+        }
+    }
+    return best;
+}
+
+template <int Q, class R, int TX, int TY, int WG_PER_CU>
+hipError_t run(const lbm_ctx *c, const void *in, void *out, bool phi_cached, const void *normal = nullptr)
+{
+    // Waves per SIMD the register allocation must leave room for.
+    constexpr int WPE = (TX * TY / 64 * WG_PER_CU + 3) / 4;
     TileGrid g;
     g.nx = c->nx;
     g.ny = c->ny;
@@ -398,21 +489,26 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out, bool phi_cached)
     g.lay = c->lay;
     g.tiles_x = (c->nx + TX - 1) / TX;
     g.tiles_y = (c->ny + TY - 1) / TY;
-    g.zchunk = choose_zchunk(c->nz, g.tiles_x * g.tiles_y, 256 * WG_PER_CU);
+    g.zchunk = balanced_zchunk(c->nz, g.tiles_x * g.tiles_y, 256 * WG_PER_CU);
     g.chunks = (c->nz + g.zchunk - 1) / g.zchunk;
     const int64_t blocks = (int64_t)g.tiles_x * g.tiles_y * g.chunks;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    if (c->nc_A != 0.0) {
+    if (normal) {
+        // Streaming pass of the split schedule.
+        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, false, WPE, true>), dim3((unsigned)blocks), dim3(TX * TY), 0,
+                           c->stream, static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega,
+                           (R)(c->A / 9.0), (R)c->beta, static_cast<const R *>(normal), nullptr);
+    } else if (c->nc_A != 0.0) {
         // Near-contact force of this state first (into the context's scratch:
         // F, then the phase field, reused when the previous step wrote it).
         R *phi = static_cast<R *>(c->scratch_nc) + 3 * c->N;
         hipError_t e = phi_cached ? launch_nc_force(c, nullptr, phi) : launch_nc_force(c, in, nullptr);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, true>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
+        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, true, WPE>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
                            static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega, (R)(c->A / 9.0),
                            (R)c->beta, static_cast<const R *>(c->scratch_nc), phi);
     } else {
-        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, false>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
+        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, false, WPE>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
                            static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega, (R)(c->A / 9.0),
                            (R)c->beta, nullptr, nullptr);
     }
@@ -432,15 +528,15 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out, bool phi_cached)
 #define LBM_CG_WG 2
 #endif
 
-hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out, bool phi_cached)
+hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out, bool phi_cached, const void *normal)
 {
     if (c->species != 2) return hipErrorNotSupported;
     if (c->storage == LBM_STORE_F32)
-        return c->q == 19 ? run<19, float, LBM_CG_TX, LBM_CG_TY, LBM_CG_WG>(c, in, out, phi_cached)
-                          : run<27, float, 32, 8, 2>(c, in, out, phi_cached);
+        return c->q == 19 ? run<19, float, LBM_CG_TX, LBM_CG_TY, LBM_CG_WG>(c, in, out, phi_cached, normal)
+                          : run<27, float, 32, 8, 2>(c, in, out, phi_cached, normal);
     if (c->storage == LBM_STORE_F64)
-        return c->q == 19 ? run<19, double, 32, 4, 2>(c, in, out, phi_cached)
-                          : run<27, double, 32, 4, 2>(c, in, out, phi_cached);
+        return c->q == 19 ? run<19, double, 32, 4, 2>(c, in, out, phi_cached, normal)
+                          : run<27, double, 32, 4, 2>(c, in, out, phi_cached, normal);
     return hipErrorInvalidValue;
 }
 

@@ -34,6 +34,7 @@ struct lbm_ctx {
     double *red_out = nullptr;   // 5 device doubles
     float *scratch_phi = nullptr; // phase field of the two-species population scheme
     void *scratch_adj = nullptr;  // co-state of the colour gradient (3 fields, layout lay3), two-species adjoint
+    void *scratch_split = nullptr; // split two-species step: phase field (N) and interface normal (3 N)
     void *adj_work = nullptr;     // lbm_adjoint_step: one stored state and two stored co-states
     double *adj_dtau = nullptr;   // lbm_adjoint_step: its dL/dtau term (one device double)
     bool owns_state = true;       // false: the state copies are caller buffers (lbm_opts.state_buffers)
@@ -67,7 +68,17 @@ hipError_t launch_adjoint_sweep2(const lbm_ctx *c, const void *state_t1, const v
 // Two-component moment step.  With the near-contact force the step also
 // writes the phase field of its output into the scratch after the force;
 // phi_cached says that the scratch already holds the phase field of `in`.
-hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out, bool phi_cached = false);
+// normal (split schedule): `in` holds post-collision moments and `normal`
+// the interface normal (three arrays of N reals); the step only streams.
+hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out, bool phi_cached = false,
+                          const void *normal = nullptr);
+
+// Split schedule of the two-component step (Sec. III.A): a phase-field
+// pass, a collision pass that relaxes the stored moments in place (with the
+// perturbation, and Guo's forcing of the near-contact force) and writes the
+// interface normal, then the streaming pass.  Scratch: c->scratch_split
+// (4 N reals: phase field, normal).  Equal to the fused step bit for bit.
+hipError_t launch_cg_split_step(const lbm_ctx *c, void *in, void *out);
 
 // Discrete adjoint of the one-species moment step; co-states in the public
 // layout, or in the stored (blocked) layout of the state if `stored`.
@@ -90,8 +101,13 @@ hipError_t launch_costate_convert(const lbm_ctx *c, const void *src, void *dst, 
 
 // Near-contact force of the two-species schemes into c->scratch_nc (three
 // arrays of N), from the phase field `phi` (N values, population scheme) or,
-// if phi is NULL, from the moment state `moments`.
+// if phi is NULL, from the moment state `moments`.  The scratch must start
+// zeroed (nc_scratch_bytes bytes): per-block flags record where the force
+// arrays may hold non-zero values.
 hipError_t launch_nc_force(const lbm_ctx *c, const void *moments, const void *phi);
+int64_t nc_blocks(const lbm_ctx *c);
+size_t nc_scratch_bytes(const lbm_ctx *c);
+uint8_t *nc_block_flags(const lbm_ctx *c);
 
 // Population scheme in place (AA pattern) on the single array `state`; odd:
 // the state has gone through an odd number of steps.

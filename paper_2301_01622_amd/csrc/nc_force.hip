@@ -15,6 +15,17 @@
 // The force of time t is computed from the phase field of the streamed
 // state, one thread per node, into three arrays of N values (x fastest);
 // the collision kernels add it with Guo's forcing.
+//
+// A film is crossed only between a node with phi < 0 and one with phi > 0,
+// both within h_max nodes of x along every axis.  The pass therefore first
+// records, per block of 64 x 4 nodes of a plane and per 16-node group of its
+// rows, whether any phi is positive and whether any is negative
+// (k_phi_signs); a block whose neighbourhood of radius h_max holds no
+// positive phi or no negative phi has F = 0 at every node, exactly as the
+// per-node search would find, and skips the search.  Its force arrays are
+// rewritten (with zeros) only if a previous pass left non-zero values there
+// (a per-block flag), so the bulk of a droplet run costs a few byte loads
+// per block.
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -41,6 +52,76 @@ __global__ __launch_bounds__(kNX *kNY) void k_phi_of_moments(const R *__restrict
     const int64_t so = lay.node(x, y, z);
     const R dr = state[so], r1 = state[kBlock + so];
     phi[(int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z)] = fma_(R(2) * r1, reciprocal<R>(R(1) + dr), R(-1));
+}
+
+// Planes per block of the sign and force passes.
+constexpr int kZB = 8;
+// Largest probe range (lbm_create refuses more).
+constexpr int kHmaxMax = 32;
+
+// Sign summary of the phase field: for the block (bx, by) of 64 x 4 nodes
+// of plane z, bit k (k = 0..3) is set if a node of x-group k (16 nodes) has
+// phi > 0, bit 4 + k if one has phi < 0.  One wave per row; each workgroup
+// covers kZB planes.
+template <class R>
+__global__ __launch_bounds__(kNX *kNY) void k_phi_signs(const R *__restrict__ phi, int nx, int ny, int nz,
+                                                        uint8_t *__restrict__ sig)
+{
+    const int x = blockIdx.x * kNX + threadIdx.x, y = blockIdx.y * kNY + threadIdx.y;
+    const int z0 = blockIdx.z * kZB, zn = min(kZB, nz - z0);
+    __shared__ unsigned int bits[kZB];
+    if (threadIdx.y == 0 && threadIdx.x < kZB) bits[threadIdx.x] = 0u;
+    R f[kZB];
+    const bool in = x < nx && y < ny;
+#pragma unroll
+    for (int k = 0; k < kZB; ++k)
+        f[k] = in && k < zn ? phi[(int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * (z0 + k))] : R(0);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kZB; ++k) {
+        const unsigned long long pos = __ballot(f[k] > R(0)), neg = __ballot(f[k] < R(0));
+        if (threadIdx.x == 0) {
+            unsigned int b = 0u;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                if ((pos >> (16 * g)) & 0xffffull) b |= 1u << g;
+                if ((neg >> (16 * g)) & 0xffffull) b |= 1u << (4 + g);
+            }
+            if (b) atomicOr(&bits[k], b);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.y == 0 && (int)threadIdx.x < zn)
+        sig[blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * (z0 + threadIdx.x))] =
+            (uint8_t)bits[threadIdx.x];
+}
+
+// Group indices (groups of width g over [0, n)) met by the coordinates
+// lo, lo+1, ..., lo+len-1 taken modulo n: at most two runs.
+struct GroupRuns {
+    int a0, n0, a1, n1;
+    __device__ int at(int i) const { return i < n0 ? a0 + i : a1 + (i - n0); }
+    __device__ int count() const { return n0 + n1; }
+};
+
+__device__ inline GroupRuns group_runs(int lo, int len, int n, int g)
+{
+    GroupRuns r{0, 0, 0, 0};
+    if (len >= n) {
+        r.n0 = (n + g - 1) / g;
+        return r;
+    }
+    int a = lo % n;
+    if (a < 0) a += n;
+    const int b = a + len - 1;
+    r.a0 = a / g;
+    if (b < n) {
+        r.n0 = b / g - r.a0 + 1;
+    } else {
+        r.n0 = (n - 1) / g - r.a0 + 1;
+        r.n1 = (b - n) / g + 1;
+    }
+    return r;
 }
 
 // One step of a probe walk: p in [0, n), |d| <= 1.
@@ -93,55 +174,107 @@ __device__ inline int closest_direction(R Gx, R Gy, R Gz)
 
 template <int Q, class R>
 __global__ __launch_bounds__(kNX *kNY) void k_nc_force(const R *__restrict__ phi, R *__restrict__ F, int nx, int ny,
-                                                       int nz, int64_t N, R half_Ah, int hmax)
+                                                       int nz, int64_t N, R half_Ah, int hmax,
+                                                       const uint8_t *__restrict__ sig, uint8_t *__restrict__ dirty)
 {
     using L = Lattice<Q>;
-    const int x = blockIdx.x * kNX + threadIdx.x, y = blockIdx.y * kNY + threadIdx.y, z = blockIdx.z;
-    if (x >= nx || y >= ny) return;
-    const int64_t sy = nx, sz = (int64_t)nx * ny;
-    const int64_t n = x + sy * y + sz * z;
-    // Offsets of the neighbouring rows, columns and planes (periodic).
-    const int64_t ox[3] = {(x == 0 ? nx - 1 : x - 1) - (int64_t)x, 0, (x == nx - 1 ? 0 : x + 1) - (int64_t)x};
-    const int64_t oy[3] = {((y == 0 ? ny - 1 : y - 1) - (int64_t)y) * sy, 0, ((y == ny - 1 ? 0 : y + 1) - (int64_t)y) * sy};
-    const int64_t oz[3] = {((z == 0 ? nz - 1 : z - 1) - (int64_t)z) * sz, 0, ((z == nz - 1 ? 0 : z + 1) - (int64_t)z) * sz};
-    R Gx = R(0), Gy = R(0), Gz = R(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
-        if (cx == 0 && cy == 0 && cz == 0) continue;
-        const R wp = R(3.0 * L::w(i)) * phi[n + ox[cx + 1] + oy[cy + 1] + oz[cz + 1]];
-        if (cx) Gx = cx > 0 ? Gx + wp : Gx - wp;
-        if (cy) Gy = cy > 0 ? Gy + wp : Gy - wp;
-        if (cz) Gz = cz > 0 ? Gz + wp : Gz - wp;
-    }
-    int found = 0;
-    if (Gx != R(0) || Gy != R(0) || Gz != R(0)) {
-        const int key = closest_direction<Q>(Gx, Gy, Gz);
-        const int dx = key / 9 - 1, dy = key / 3 % 3 - 1, dz = key % 3 - 1;
-        // Probes x + k c*, k = 1..h_max, each coordinate stepped with its own
-        // wrap, stopping at the first film; four loads are issued at a time.
-        bool seen = phi[n] < R(0);
-        int px = x, py = y, pz = z;
-        for (int k0 = 1; k0 <= hmax && !found; k0 += 4) {
-            R f[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                px = step_wrap(px, dx, nx);
-                py = step_wrap(py, dy, ny);
-                pz = step_wrap(pz, dz, nz);
-                f[k] = phi[px + sy * py + sz * pz];
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (k0 + k <= hmax && !found) {
-                    if (f[k] < R(0)) seen = true;
-                    else if (f[k] > R(0) && seen) found = 1;
-                }
+    const int x = blockIdx.x * kNX + threadIdx.x, y = blockIdx.y * kNY + threadIdx.y;
+    const int tid = threadIdx.x + kNX * threadIdx.y;
+    const int z0 = blockIdx.z * kZB, zn = min(kZB, nz - z0);
+    const int gx = (nx + kNX - 1) / kNX, gy = (ny + kNY - 1) / kNY;
+    auto blk_of = [&](int z) { return blockIdx.x + (int64_t)gx * (blockIdx.y + (int64_t)gy * z); };
+    // Signs of the window of planes z0 - hmax .. z0 + zn - 1 + hmax (wrapped)
+    // over the x-groups and block rows within hmax of this block, and the
+    // dirty flags of the block's planes, read before any is rewritten.
+    const int W = zn + 2 * hmax;
+    __shared__ unsigned int s_bits[kZB + 2 * kHmaxMax];
+    __shared__ uint8_t s_dirty[kZB];
+    if (tid < W) s_bits[tid] = 0u;
+    if (tid < zn) s_dirty[tid] = dirty[blk_of(z0 + tid)];
+    __syncthreads();
+    {
+        const GroupRuns gxr = group_runs(blockIdx.x * kNX - hmax, kNX + 2 * hmax, nx, 16);
+        const GroupRuns gyr = group_runs(blockIdx.y * kNY - hmax, kNY + 2 * hmax, ny, kNY);
+        const int cx = gxr.count(), pairs = cx * gyr.count(), total = pairs * W;
+        for (int t = tid; t < total; t += kNX * kNY) {
+            const int w = t / pairs, r = t - w * pairs;
+            const int G = gxr.at(r % cx), by = gyr.at(r / cx);
+            int zw = (z0 - hmax + w) % nz;
+            if (zw < 0) zw += nz;
+            const unsigned v = sig[G / 4 + (int64_t)gx * (by + (int64_t)gy * zw)];
+            const unsigned b = ((v >> (G % 4)) & 1u) | (((v >> (4 + G % 4)) & 1u) << 1);
+            if (b) atomicOr(&s_bits[w], b);
         }
     }
-    F[n] = found ? half_Ah * Gx : R(0);
-    F[N + n] = found ? half_Ah * Gy : R(0);
-    F[2 * N + n] = found ? half_Ah * Gz : R(0);
+    __syncthreads();
+    const bool in = x < nx && y < ny;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    for (int k = 0; k < zn; ++k) {
+        const int z = z0 + k;
+        // Is there a phi > 0 and a phi < 0 within hmax of the block's plane z?
+        unsigned int b = 0u;
+        for (int w = k; w <= k + 2 * hmax; ++w) b |= s_bits[w];
+        if (b != 3u) {
+            // No film can be crossed from any node of this plane: F = 0.
+            if (s_dirty[k]) {
+                if (in) {
+                    const int64_t n = x + sy * y + sz * z;
+                    F[n] = R(0);
+                    F[N + n] = R(0);
+                    F[2 * N + n] = R(0);
+                }
+                if (tid == 0) dirty[blk_of(z)] = 0;
+            }
+            continue;
+        }
+        if (tid == 0 && !s_dirty[k]) dirty[blk_of(z)] = 1;
+        if (!in) continue;
+        const int64_t n = x + sy * y + sz * z;
+        // Offsets of the neighbouring rows, columns and planes (periodic).
+        const int64_t ox[3] = {(x == 0 ? nx - 1 : x - 1) - (int64_t)x, 0, (x == nx - 1 ? 0 : x + 1) - (int64_t)x};
+        const int64_t oy[3] = {((y == 0 ? ny - 1 : y - 1) - (int64_t)y) * sy, 0,
+                               ((y == ny - 1 ? 0 : y + 1) - (int64_t)y) * sy};
+        const int64_t oz[3] = {((z == 0 ? nz - 1 : z - 1) - (int64_t)z) * sz, 0,
+                               ((z == nz - 1 ? 0 : z + 1) - (int64_t)z) * sz};
+        R Gx = R(0), Gy = R(0), Gz = R(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+            if (cx == 0 && cy == 0 && cz == 0) continue;
+            const R wp = R(3.0 * L::w(i)) * phi[n + ox[cx + 1] + oy[cy + 1] + oz[cz + 1]];
+            if (cx) Gx = cx > 0 ? Gx + wp : Gx - wp;
+            if (cy) Gy = cy > 0 ? Gy + wp : Gy - wp;
+            if (cz) Gz = cz > 0 ? Gz + wp : Gz - wp;
+        }
+        int found = 0;
+        if (Gx != R(0) || Gy != R(0) || Gz != R(0)) {
+            const int key = closest_direction<Q>(Gx, Gy, Gz);
+            const int dx = key / 9 - 1, dy = key / 3 % 3 - 1, dz = key % 3 - 1;
+            // Probes x + k c*, k = 1..h_max, each coordinate stepped with its
+            // own wrap, stopping at the first film; four loads at a time.
+            bool seen = phi[n] < R(0);
+            int px = x, py = y, pz = z;
+            for (int k0 = 1; k0 <= hmax && !found; k0 += 4) {
+                R f[4];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    px = step_wrap(px, dx, nx);
+                    py = step_wrap(py, dy, ny);
+                    pz = step_wrap(pz, dz, nz);
+                    f[kk] = phi[px + sy * py + sz * pz];
+                }
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    if (k0 + kk <= hmax && !found) {
+                        if (f[kk] < R(0)) seen = true;
+                        else if (f[kk] > R(0) && seen) found = 1;
+                    }
+            }
+        }
+        F[n] = found ? half_Ah * Gx : R(0);
+        F[N + n] = found ? half_Ah * Gy : R(0);
+        F[2 * N + n] = found ? half_Ah * Gz : R(0);
+    }
 }
 
 template <class R>
@@ -155,16 +288,39 @@ hipError_t run(const lbm_ctx *c, const void *moments, const R *phi_in, R *phi_bu
                            c->nx, c->ny, phi_buf);
         phi = phi_buf;
     }
+    uint8_t *sig = nc_block_flags(c), *dirty = sig + nc_blocks(c);
+    const dim3 zgrid(grid.x, grid.y, (c->nz + kZB - 1) / kZB);
+    hipLaunchKernelGGL((k_phi_signs<R>), zgrid, block, 0, c->stream, phi, c->nx, c->ny, c->nz, sig);
+    if (c->nc_hmax > kHmaxMax) return hipErrorInvalidValue;
     if (c->q == 19)
-        hipLaunchKernelGGL((k_nc_force<19, R>), grid, block, 0, c->stream, phi, F, c->nx, c->ny, c->nz, c->N,
-                           (R)(0.5 * c->nc_A), c->nc_hmax);
+        hipLaunchKernelGGL((k_nc_force<19, R>), zgrid, block, 0, c->stream, phi, F, c->nx, c->ny, c->nz, c->N,
+                           (R)(0.5 * c->nc_A), c->nc_hmax, sig, dirty);
     else
-        hipLaunchKernelGGL((k_nc_force<27, R>), grid, block, 0, c->stream, phi, F, c->nx, c->ny, c->nz, c->N,
-                           (R)(0.5 * c->nc_A), c->nc_hmax);
+        hipLaunchKernelGGL((k_nc_force<27, R>), zgrid, block, 0, c->stream, phi, F, c->nx, c->ny, c->nz, c->N,
+                           (R)(0.5 * c->nc_A), c->nc_hmax, sig, dirty);
     return hipGetLastError();
 }
 
 } // namespace
+
+int64_t nc_blocks(const lbm_ctx *c)
+{
+    return (int64_t)((c->nx + kNX - 1) / kNX) * ((c->ny + kNY - 1) / kNY) * c->nz;
+}
+
+size_t nc_scratch_bytes(const lbm_ctx *c)
+{
+    // F (3 N reals), the moment scheme's phase field (N reals), then the
+    // sign summary and the dirty flag of every block (one byte each).
+    const size_t reals = (size_t)c->N * (c->scheme == LBM_SCHEME_MOMENT ? 4 : 3);
+    return c->elem * reals + 2 * (size_t)nc_blocks(c);
+}
+
+uint8_t *nc_block_flags(const lbm_ctx *c)
+{
+    const size_t reals = (size_t)c->N * (c->scheme == LBM_SCHEME_MOMENT ? 4 : 3);
+    return static_cast<uint8_t *>(c->scratch_nc) + c->elem * reals;
+}
 
 hipError_t launch_nc_force(const lbm_ctx *c, const void *moments, const void *phi)
 {

@@ -40,27 +40,13 @@ import torch
 from . import inputs
 from .lbm import LBM
 
-TAU, SIGMA, BETA, HMAX = 0.8, 0.01, 0.7, 4
-CASES = {
-    "off_axis": dict(b=0.85, u_rel=0.5, A_h=0.01),
-    "head_on": dict(b=0.0, u_rel=0.25, A_h=0.01),
-    "coalescence": dict(b=0.85, u_rel=0.5, A_h=0.0),
-    "head_on_coalescence": dict(b=0.0, u_rel=0.25, A_h=0.0),
-}
+TAU, SIGMA, BETA, HMAX = inputs.PAPER_TAU, inputs.PAPER_SIGMA, inputs.PAPER_BETA, inputs.PAPER_HMAX
+CASES = inputs.PAPER_CASES
 
 
 def setup(case: str, n: int = 128):
     """(rho1, rho2, u) for the case on an n^3 box (drops of diameter 30 n/128)."""
-    c = CASES[case]
-    scale = n / 128.0
-    D = 30.0 * scale
-    u_cap = SIGMA / (1.0 * (TAU - 0.5) / 3.0)       # sigma / (rho nu)
-    v = 0.5 * c["u_rel"] * u_cap
-    dy = c["b"] * D
-    cx, cy, cz = n / 2.0, n / 2.0, n / 2.0
-    sep = 38.0 * scale
-    centres = [(cx - sep / 2, cy - dy / 2, cz), (cx + sep / 2, cy + dy / 2, cz)]
-    return inputs.droplets((n, n, n), centres=centres, radius=D / 2, velocities=[(v, 0, 0), (-v, 0, 0)])
+    return inputs.paper_collision(case, n)
 
 
 def probes(n: int = 128):

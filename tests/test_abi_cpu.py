@@ -66,7 +66,7 @@ def test_create_rejects_bad_arguments_before_device(grid, q, tau, species, schem
 
 @pytest.mark.parametrize("species,scheme,split", [
     (1, 0, 2),     # split is 0 or 1
-    (2, 0, 1),     # split approach: one species
+    (2, 1, 1),     # split approach: moment scheme only (two species too)
     (1, 1, 1),     # split approach: moment scheme only
     (1, 2, 1),
 ])

@@ -76,3 +76,53 @@ def test_split_context_rejects_step_state():
         sim.step_state(a, b)
     assert e.value.code == _lib.LBM_ESTATE
     sim.close()
+
+
+def _droplet_state(oracle, shape, gap=3.0, R=5.0):
+    nz, ny, nx = shape
+    c1 = (nx / 2 - gap / 2 - R, ny / 2 + 0.3, nz / 2 - 0.2)
+    c2 = (nx / 2 + gap / 2 + R, ny / 2 - 0.4, nz / 2 + 0.1)
+    r1, r2, u = I.droplets(shape, centres=[c1, c2], radius=R, velocities=[(0.02, 0, 0), (-0.02, 0, 0)], width=1.0)
+    H = oracle.equilibrium_moments2(r1, r2, u)
+    # a generic non-equilibrium part, so that the relaxation matters
+    H[5:] += 1e-3 * np.random.default_rng(77).standard_normal(H[5:].shape)
+    return np.ascontiguousarray(H)
+
+
+def _run2(H, q, steps, storage, split, nc_A=0.0):
+    from paper_2301_01622_amd.lbm import LBM
+    nf, nz, ny, nx = H.shape
+    sim = LBM((nx, ny, nz), q, 0.8, species=2, storage=storage, sigma=0.01, beta=0.7, split=split, nc_A=nc_A,
+              nc_hmax=4 if nc_A else 0)
+    sim.set_moments(torch.from_numpy(H).cuda())
+    sim.step(steps)
+    out = sim.get_moments(torch.float64).cpu().numpy()
+    mem = sim.memory_info()
+    sim.close()
+    return out, mem
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
+@pytest.mark.parametrize("nc_A", [0.0, 0.05])
+def test_split_two_species_equals_fused_and_oracle(oracle, q, storage, tol, nc_A):
+    """The colour-gradient step as a phase pass, a collision pass and a
+    streaming pass, on a ragged 70 x 21 x 13 box (several tiles, partial
+    ones) with two drops three nodes apart, 6 steps, with and without the
+    near-contact force: equal to the fused step bit for bit, and to the
+    oracle within the fused step's bound."""
+    shape = (13, 21, 70)
+    _say(f"two-species split {shape} D3Q{q} {storage} nc_A={nc_A} 6 steps")
+    H = _droplet_state(oracle, shape)
+    split, mem_s = _run2(H, q, 6, storage, True, nc_A)
+    fused, mem_f = _run2(H, q, 6, storage, False, nc_A)
+    np.testing.assert_array_equal(split, fused)
+    A = oracle.sigma_to_A(0.01, 0.8)
+    ref = oracle.cg_moment_run(H, q, 0.8, A, 0.7, 6, Ah=nc_A, hmax=4 if nc_A else 0)
+    err = np.abs(split - ref).max()
+    _say(f"  max err vs oracle {err:.3e}")
+    assert err <= tol
+    N = int(np.prod(shape))
+    elem = 8 if storage == "f64" else 4
+    assert mem_f[1] == 22 * elem * N and mem_s[1] == (52 if nc_A else 49) * elem * N
+    assert mem_s[0] == mem_f[0] + 4 * elem * N
