@@ -114,8 +114,12 @@ __global__ __launch_bounds__(TX *TY, WPE) void k_cg_tile(const R *__restrict__ i
     static_assert(RING <= NT && OUTER <= NT, "halo rings must fit one pass");
     constexpr int NS = kLdsSlots<Q>;
     using SL = SlotLayout<Q, TX, TY>;
-    __shared__ R lds_h[SL::total()];  // shifted mixture populations
-    __shared__ R lds_f[SL::total()];  // species-1 populations
+    // Per published direction and node: the shifted mixture population h~
+    // and the species-1 population f1, side by side (one wide LDS access).
+    struct alignas(2 * sizeof(R)) HF {
+        R h, f;
+    };
+    __shared__ HF lds_hf[SL::total()];
     __shared__ R lds_phi[3 * FN];  // phase field of three planes
 
     const int b = xcd_tile_id();
@@ -338,8 +342,7 @@ __global__ __launch_bounds__(TX *TY, WPE) void k_cg_tile(const R *__restrict__ i
                 f1_moving += f1;
                 const int s = lds_slot<Q>(cz, sl);
                 if (s >= 0) {
-                    lds_h[lds_at(s, ba0, bb0)] = hv;
-                    lds_f[lds_at(s, ba0, bb0)] = f1;
+                    lds_hf[lds_at(s, ba0, bb0)] = HF{hv, f1};
                 } else {  // own column (0, 0, +-1)
                     own_h[cz + 1] = hv;
                     own_f[cz + 1] = f1;
@@ -377,8 +380,7 @@ __global__ __launch_bounds__(TX *TY, WPE) void k_cg_tile(const R *__restrict__ i
                 // directions that leave it beside the tile; it skips them.
                 if (!ROW && !(t == 0 ? (ring_y >= 0 && ring_y < TY) : (t > 0 ? ring_y < TY : ring_y >= 0)))
                     continue;
-                lds_h[lds_at(s, bar, bbr)] = hv;
-                lds_f[lds_at(s, bar, bbr)] = f1;
+                lds_hf[lds_at(s, bar, bbr)] = HF{hv, f1};
             }
     };
     using Up = std::integral_constant<int, 1>;
@@ -396,8 +398,9 @@ __global__ __launch_bounds__(TX *TY, WPE) void k_cg_tile(const R *__restrict__ i
             } else if (lds_slot<Q>(CZ, sl) >= 0) {
                 const int s = lds_slot<Q>(CZ, sl);
                 const int idx = lds_at(s, ba0, bb0) - cy * SL::width(s) - cx;
-                fh.v[sl] = lds_h[idx];
-                r1 += lds_f[idx];
+                const HF v = lds_hf[idx];
+                fh.v[sl] = v.h;
+                r1 += v.f;
             }
         }
         accumulate_layer<Q, CZ, R>(ac.m, fh);

@@ -1,0 +1,136 @@
+"""Writes the oracle's observables of two long two-component droplet runs to
+JSON files beside this script; the GPU tests compare their FP32 runs with
+them.  Calls only the oracle (oracle/) and the seeded input generators.
+
+Runs (D3Q19, tau = 0.8, sigma = 0.01, beta = 0.7, the colour-gradient step of
+Sec. III.A with the operators of Sec. III.B, FP64):
+
+  c3_recipe_128 : the two-drop collision of the 512 x 256 x 256 workload at a
+                  128^3 fallback size (drops of radius 20 at (34, 59, 64) and
+                  (94, 69, 64), u_x = +-0.05, tanh width 1.5), 2000 steps;
+  head_on_128   : the paper's head-on validation collision (Sec. IV, Figs.
+                  4-5: drops of diameter 30, b = 0, U_rel = 0.25) with the
+                  near-contact force A_h = 0.01 (probe range 4), 2000 steps.
+
+Each case runs twice: from the initial state, and from the same state rounded
+to FP32 (a perturbation of the size an FP32 run starts with).  Every 100 steps
+the script records the observables (observables() below) of both runs, and
+at a few steps the 11 moments at sampled nodes; the spread between the two
+runs sets the GPU tests' tolerance.  The files are rewritten after every
+100 steps, so a partial run is usable.
+
+    python tests/golden/oracle_droplet_runs.py [case ...]   # about 1-2 h per case on 8 cores
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+TAU, SIGMA, BETA, Q = 0.8, 0.01, 0.7, 19
+STEPS, EVERY = 2000, 100
+SAMPLE_STEPS = (100, 200, 300, 500, 1000, 2000)
+
+
+def observables(M: np.ndarray) -> dict:
+    """Diagnostics of an 11-field state (rho1, rho2, j, P), shape
+    (11, n, n, n), x fastest: mean of rho1 over nodes with rho1 > 0.5; the x
+    and y centroids of rho1 over the half boxes x < n/2 and x >= n/2; kinetic
+    energy sum |j|^2 / (2 rho); phi = (rho1 - rho2)/(rho1 + rho2) at node
+    (n/2 - 1) along every axis; total rho1."""
+    r1, r2 = M[0], M[1]
+    n = r1.shape[2]
+    rho = r1 + r2
+    x = np.arange(n, dtype=np.float64)[None, None, :]
+    y = np.arange(n, dtype=np.float64)[None, :, None]
+    half = [x < n / 2.0, x >= n / 2.0]
+    cent = []
+    for m in half:
+        w = r1 * m
+        s = w.sum()
+        cent += [float((w * x).sum() / s), float((w * y).sum() / s)]
+    c = n // 2 - 1
+    return {
+        "mean_rho1": float(r1[r1 > 0.5].mean()),
+        "centroids": cent,
+        "kinetic_energy": float(((M[2] ** 2 + M[3] ** 2 + M[4] ** 2) / (2.0 * rho)).sum()),
+        "phi_centre": float((r1[c, c, c] - r2[c, c, c]) / rho[c, c, c]),
+        "mass_rho1": float(r1.sum()),
+    }
+
+
+def sample_nodes(n: int, case: str):
+    """(z, y, x) nodes: along the collision axis through the gap between the
+    drops, on the drop surfaces, in the drop cores, in the carrier, corners."""
+    c = n // 2 - 1
+    nodes = [(c, c, x) for x in range(c - 10, c + 12, 2)]
+    if case == "c3_recipe_128":
+        nodes += [(64, 59, 54), (64, 69, 74), (64, 59, 34), (64, 69, 94), (64, 79, 64), (64, 49, 64)]
+    else:
+        nodes += [(c, c, c - 30), (c, c, c + 30), (c, c + 15, c - 19), (c, c - 15, c + 19), (c + 15, c, c - 19)]
+    nodes += [(0, 0, 0), (n - 1, n - 1, n - 1), (c, 0, c), (10, 100, 20)]
+    return sorted(set(nodes))
+
+
+def initial_state(case: str):
+    import oracle
+    from paper_2301_01622_amd import inputs
+    if case == "c3_recipe_128":
+        r1, r2, u = inputs.droplet_collision_128()
+        A_h = 0.0
+    elif case == "head_on_128":
+        r1, r2, u = inputs.paper_collision("head_on", 128)
+        A_h = inputs.PAPER_CASES["head_on"]["A_h"]
+    else:
+        raise ValueError(case)
+    return oracle.equilibrium_moments2(r1, r2, u), A_h
+
+
+def run(case: str) -> str:
+    import oracle
+    oracle._load()
+    H0, A_h = initial_state(case)
+    hmax = 4 if A_h else 0
+    A = oracle.sigma_to_A(SIGMA, TAU)
+    n = H0.shape[-1]
+    nodes = sample_nodes(n, case)
+    states = {"x0": H0, "x0_fp32": H0.astype(np.float32).astype(np.float64)}
+    out = {
+        "case": case, "n": n, "lattice": "D3Q19", "tau": TAU, "sigma": SIGMA, "beta": BETA, "A_h": A_h,
+        "h_max": hmax, "steps": STEPS, "every": EVERY,
+        "source": "oracle.cg_moment_run (FP64), written by tests/golden/oracle_droplet_runs.py",
+        "runs": {"x0": "the initial state", "x0_fp32": "the initial state rounded to FP32"},
+        "t": [], "obs": {k: [] for k in states}, "sample_nodes": nodes, "samples": {k: {} for k in states},
+    }
+    path = os.path.join(HERE, f"oracle_{case}.json")
+    t = 0
+    t0 = time.time()
+    while True:
+        out["t"].append(t)
+        for k, H in states.items():
+            out["obs"][k].append(observables(H))
+            if t in SAMPLE_STEPS:
+                out["samples"][k][str(t)] = [[float(H[f, z, y, x]) for f in range(11)] for (z, y, x) in nodes]
+        with open(path + ".tmp", "w") as fh:
+            json.dump(out, fh)
+        os.replace(path + ".tmp", path)
+        print(f"{case}: t={t} ({time.time() - t0:.0f} s)", flush=True)
+        if t >= STEPS:
+            break
+        for k in states:
+            states[k] = oracle.cg_moment_run(states[k], Q, TAU, A, BETA, EVERY, Ah=A_h, hmax=hmax)
+        t += EVERY
+    return path
+
+
+if __name__ == "__main__":
+    for c in (sys.argv[1:] or ["c3_recipe_128", "head_on_128"]):
+        print(run(c), flush=True)
