@@ -126,3 +126,52 @@ def test_full_size_reduced_precision_report():
         assert report["max_abs_err"]["rho"] <= 16 * eps * 3 * umax * np.sqrt(T)
         del got, ug
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_reduced_precision_against_oracle_at_128(storage):
+    """The same recipe at a 128^3 fallback size for the full 2000 steps
+    against the FP64 oracle's state at 512 sampled nodes and its x-z averaged
+    shear-wave profile u_x(y) every 500 steps (tests/golden/
+    oracle_c4_recipe_128.json, written by oracle_shear_run.py, which calls
+    only the oracle).  Per-field errors are printed and bounded by the
+    storage format as above (FP64 storage: 1e-12)."""
+    import os
+    from paper_2301_01622_amd.lbm import LBM
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_c4_recipe_128.json")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/oracle_c4_recipe_128.json not written yet (tests/golden/oracle_shear_run.py)")
+    g = json.load(open(path))
+    n, tau, every = g["n"], g["tau"], g["every"]
+    print(f"[gpu] 128^3 D3Q27 {storage} against the oracle, {g['t'][-1]} steps", flush=True)
+    rho, u = I.shear_wave_with_noise(n, seed=I.SEED_C4, u0=0.01, noise=1e-4)
+    sim = LBM((n, n, n), 27, tau, storage=storage)
+    sim.set_equilibrium(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
+    idx = np.array(g["sample_nodes"])
+    for i, t in enumerate(g["t"]):
+        if i:
+            sim.step(every)
+        M = sim.get_moments(torch.float64, device="cpu").numpy()
+        got = M[:, idx[:, 0], idx[:, 1], idx[:, 2]].T
+        ref = np.array(g["samples"][i])
+        ug, ur = got[:, 1:4] / got[:, :1], ref[:, 1:4] / ref[:, :1]
+        prof = (M[1] / M[0]).mean(axis=(0, 2))
+        report = {
+            "t": t, "storage": storage,
+            "max_abs_err": {"rho": float(np.abs(got[:, 0] - ref[:, 0]).max()), "u": float(np.abs(ug - ur).max()),
+                            "P": float(np.abs(got[:, 4:] - ref[:, 4:]).max())},
+            "rel_l2_err_u": float(np.sqrt(((ug - ur) ** 2).sum() / (ur ** 2).sum())),
+            "profile_err": float(np.abs(prof - np.array(g["ux_profile"][i])).max()),
+        }
+        print(f"[gpu] storage error report {json.dumps(report)}", flush=True)
+        umax = np.abs(ur).max()
+        if storage == "f64":
+            bound_u = bound_rho = 1e-12
+        else:
+            eps = 2.0 ** -(MANTISSA[storage] + 1)
+            bound_u = 16 * eps * umax * np.sqrt(max(t, 1))
+            bound_rho = 16 * eps * 3 * umax * np.sqrt(max(t, 1))
+        assert report["max_abs_err"]["u"] <= bound_u
+        assert report["max_abs_err"]["rho"] <= bound_rho
+        assert report["profile_err"] <= bound_u
+    sim.close()
