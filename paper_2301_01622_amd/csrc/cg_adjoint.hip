@@ -87,12 +87,25 @@ __device__ __forceinline__ float sqrt_<float>(float x)
 
 // LSTORED: co-states in the stored (blocked) layout of the state instead of
 // the public one.
+// Launch shapes: the first pass is sized for LBM_CGA_WG resident workgroups
+// per CU (200 VGPRs at D3Q19 FP32; three would spill 141); the second marches
+// 64 x LBM_CGA_PHI_TY tiles in z-chunks sized for LBM_CGA_PHI_WG resident
+// workgroups per CU (64 x 8 in 64-plane chunks on 512 x 256 x 256: 12 % faster
+// than whole-column 64 x 16 tiles, one workgroup per CU).
+#ifndef LBM_CGA_WG
+#define LBM_CGA_WG 2
+#endif
+#ifndef LBM_CGA_PHI_TY
+#define LBM_CGA_PHI_TY 8
+#endif
+#ifndef LBM_CGA_PHI_WG
+#define LBM_CGA_PHI_WG 4
+#endif
+
 template <int Q, class R, int TX, int TY, bool LSTORED>
-__global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(const R *__restrict__ state, const R *__restrict__ lam_in,
-                                                            R *__restrict__ lam_out, R *__restrict__ gG, TileGrid g,
-                                                            MomentLayout lay3,
-                                                            R omega, R A9, R beta, double tau,
-                                                            double *__restrict__ partials)
+__global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(
+    const R *__restrict__ state, const R *__restrict__ lam_in, R *__restrict__ lam_out, R *__restrict__ gG, TileGrid g,
+    MomentLayout lay3, R omega, R A9, R beta, double tau, double *__restrict__ partials)
 {
     constexpr int NT = TX * TY;
     constexpr int HX = TX + 2, HY = TY + 2, HN = HX * HY;
@@ -505,7 +518,7 @@ hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *la
     g.lay = c->lay;
     g.tiles_x = (c->nx + TX - 1) / TX;
     g.tiles_y = (c->ny + TY - 1) / TY;
-    g.zchunk = choose_zchunk(c->nz, g.tiles_x * g.tiles_y, 256 * 2);
+    g.zchunk = choose_zchunk(c->nz, g.tiles_x * g.tiles_y, 256 * LBM_CGA_WG);
     g.chunks = (c->nz + g.zchunk - 1) / g.zchunk;
     const int64_t blocks = (int64_t)g.tiles_x * g.tiles_y * g.chunks;
     if (blocks > 5 * kReduceBlocks) return hipErrorInvalidConfiguration;
@@ -517,12 +530,13 @@ hipError_t run(const lbm_ctx *c, const void *state, const void *lam_in, void *la
     if (e != hipSuccess) return e;
     TileGrid gp = g;
     gp.tiles_x = (c->nx + 63) / 64;
-    gp.tiles_y = (c->ny + 15) / 16;
-    gp.zchunk = choose_zchunk(c->nz, gp.tiles_x * gp.tiles_y, 256);
+    gp.tiles_y = (c->ny + LBM_CGA_PHI_TY - 1) / LBM_CGA_PHI_TY;
+    gp.zchunk = choose_zchunk(c->nz, gp.tiles_x * gp.tiles_y, 256 * LBM_CGA_PHI_WG);
     gp.chunks = (c->nz + gp.zchunk - 1) / gp.zchunk;
     const int64_t pblocks = (int64_t)gp.tiles_x * gp.tiles_y * gp.chunks;
     if (pblocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_cg_adjoint_phi<Q, R, 64, 16, LSTORED>), dim3((unsigned)pblocks), dim3(1024), 0, c->stream,
+    hipLaunchKernelGGL((k_cg_adjoint_phi<Q, R, 64, LBM_CGA_PHI_TY, LSTORED>), dim3((unsigned)pblocks),
+                       dim3(64 * LBM_CGA_PHI_TY), 0, c->stream,
                        static_cast<const R *>(state), static_cast<const R *>(gG), static_cast<R *>(lam_out), gp, c->lay3);
     e = hipGetLastError();
     if (e != hipSuccess || !dtau) return e;

@@ -479,35 +479,43 @@ inline int balanced_zchunk(int nz, int tiles, int slots)
     return best;
 }
 
-template <int Q, class R, int TX, int TY, int WG_PER_CU>
+// Resident workgroups per CU each variant is sized for: WG for the plain
+// step, WGF for the step with the near-contact force, WGC for the streaming
+// pass of the split schedule.
+template <int Q, class R, int TX, int TY, int WG, int WGF, int WGC>
 hipError_t run(const lbm_ctx *c, const void *in, void *out, bool phi_cached, const void *normal = nullptr)
 {
     // Waves per SIMD the register allocation must leave room for.
-    constexpr int WPE = (TX * TY / 64 * WG_PER_CU + 3) / 4;
+    constexpr int WPE = (TX * TY / 64 * WG + 3) / 4, WPEF = (TX * TY / 64 * WGF + 3) / 4,
+                  WPEC = (TX * TY / 64 * WGC + 3) / 4;
+    auto grid = [&](int wg, TileGrid &g) -> int64_t {
+        g.nx = c->nx;
+        g.ny = c->ny;
+        g.nz = c->nz;
+        g.N = c->N;
+        g.lay = c->lay;
+        g.tiles_x = (c->nx + TX - 1) / TX;
+        g.tiles_y = (c->ny + TY - 1) / TY;
+        g.zchunk = balanced_zchunk(c->nz, g.tiles_x * g.tiles_y, 256 * wg);
+        g.chunks = (c->nz + g.zchunk - 1) / g.zchunk;
+        return (int64_t)g.tiles_x * g.tiles_y * g.chunks;
+    };
     TileGrid g;
-    g.nx = c->nx;
-    g.ny = c->ny;
-    g.nz = c->nz;
-    g.N = c->N;
-    g.lay = c->lay;
-    g.tiles_x = (c->nx + TX - 1) / TX;
-    g.tiles_y = (c->ny + TY - 1) / TY;
-    g.zchunk = balanced_zchunk(c->nz, g.tiles_x * g.tiles_y, 256 * WG_PER_CU);
-    g.chunks = (c->nz + g.zchunk - 1) / g.zchunk;
-    const int64_t blocks = (int64_t)g.tiles_x * g.tiles_y * g.chunks;
+    const bool force = c->nc_A != 0.0 && !normal;
+    const int64_t blocks = grid(normal ? WGC : force ? WGF : WG, g);
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
     if (normal) {
         // Streaming pass of the split schedule.
-        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, false, WPE, true>), dim3((unsigned)blocks), dim3(TX * TY), 0,
+        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, false, WPEC, true>), dim3((unsigned)blocks), dim3(TX * TY), 0,
                            c->stream, static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega,
                            (R)(c->A / 9.0), (R)c->beta, static_cast<const R *>(normal), nullptr);
-    } else if (c->nc_A != 0.0) {
+    } else if (force) {
         // Near-contact force of this state first (into the context's scratch:
         // F, then the phase field, reused when the previous step wrote it).
         R *phi = static_cast<R *>(c->scratch_nc) + 3 * c->N;
         hipError_t e = phi_cached ? launch_nc_force(c, nullptr, phi) : launch_nc_force(c, in, nullptr);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, true, WPE>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
+        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, true, WPEF>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
                            static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega, (R)(c->A / 9.0),
                            (R)c->beta, static_cast<const R *>(c->scratch_nc), phi);
     } else {
@@ -520,26 +528,37 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out, bool phi_cached, con
 
 } // namespace
 
-// D3Q19 FP32 tiles: 64 x 4 nodes (full 64-wide rows of the stored blocks),
-// z-chunks sized for two resident workgroups per CU (on 512 x 256 x 256 each
-// workgroup marches the whole column).  Measured against 32 x 8, 64 x 8,
-// 32 x 16 and 128 x 4 tiles and other chunkings; the shape is a compile-time
-// choice (LBM_CG_TX, LBM_CG_TY, LBM_CG_WG).
+// D3Q19 FP32 tiles: 64 x 4 nodes (full 64-wide rows of the stored blocks).
+// The plain step is sized for three resident workgroups per CU (166 VGPRs,
+// no spills; 4-5 % faster than two on 512 x 256 x 256, where each workgroup
+// marches a third of the column).  The step with the near-contact force
+// (194 VGPRs) and the streaming pass of the split schedule (which spills at
+// three) stay at two.  Measured against 32 x 8, 64 x 8, 32 x 16 and 128 x 4
+// tiles and other chunkings; the shape is a compile-time choice (LBM_CG_TX,
+// LBM_CG_TY, LBM_CG_WG, LBM_CG_WGF, LBM_CG_WGC).
 #ifndef LBM_CG_TX
 #define LBM_CG_TX 64
 #define LBM_CG_TY 4
-#define LBM_CG_WG 2
+#endif
+#ifndef LBM_CG_WG
+#define LBM_CG_WG 3
+#endif
+#ifndef LBM_CG_WGF
+#define LBM_CG_WGF 2
+#endif
+#ifndef LBM_CG_WGC
+#define LBM_CG_WGC 2
 #endif
 
 hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out, bool phi_cached, const void *normal)
 {
     if (c->species != 2) return hipErrorNotSupported;
     if (c->storage == LBM_STORE_F32)
-        return c->q == 19 ? run<19, float, LBM_CG_TX, LBM_CG_TY, LBM_CG_WG>(c, in, out, phi_cached, normal)
-                          : run<27, float, 32, 8, 2>(c, in, out, phi_cached, normal);
+        return c->q == 19 ? run<19, float, LBM_CG_TX, LBM_CG_TY, LBM_CG_WG, LBM_CG_WGF, LBM_CG_WGC>(c, in, out, phi_cached, normal)
+                          : run<27, float, 32, 8, 2, 2, 2>(c, in, out, phi_cached, normal);
     if (c->storage == LBM_STORE_F64)
-        return c->q == 19 ? run<19, double, 32, 4, 2>(c, in, out, phi_cached, normal)
-                          : run<27, double, 32, 4, 2>(c, in, out, phi_cached, normal);
+        return c->q == 19 ? run<19, double, 32, 4, 2, 2, 2>(c, in, out, phi_cached, normal)
+                          : run<27, double, 32, 4, 2, 2, 2>(c, in, out, phi_cached, normal);
     return hipErrorInvalidValue;
 }
 

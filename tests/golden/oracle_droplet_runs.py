@@ -17,9 +17,11 @@ to FP32 (a perturbation of the size an FP32 run starts with).  Every 100 steps
 the script records the observables (observables() below) of both runs, and
 at a few steps the 11 moments at sampled nodes; the spread between the two
 runs sets the GPU tests' tolerance.  The files are rewritten after every
-100 steps, so a partial run is usable.
+100 steps, so a partial run is usable.  With --state-dir DIR the two
+states are also saved there after every 100 steps, and a later call with
+the same DIR resumes from the last recorded step.
 
-    python tests/golden/oracle_droplet_runs.py [case ...]   # about 1-2 h per case on 8 cores
+    python tests/golden/oracle_droplet_runs.py [--state-dir DIR] [case ...]   # about 1-2 h per case on 8 cores
 """
 from __future__ import annotations
 
@@ -94,7 +96,7 @@ def initial_state(case: str):
     return oracle.equilibrium_moments2(r1, r2, u), A_h
 
 
-def run(case: str) -> str:
+def run(case: str, state_dir: str | None = None) -> str:
     import oracle
     oracle._load()
     H0, A_h = initial_state(case)
@@ -112,16 +114,37 @@ def run(case: str) -> str:
     }
     path = os.path.join(HERE, f"oracle_{case}.json")
     t = 0
+    # Saved states carry their step in the file name, so a kill between
+    # writing them and the JSON file leaves a consistent pair behind.
+    saved = lambda k, step: os.path.join(state_dir, f"{case}_{k}_t{step}.npy")
+    if state_dir:
+        os.makedirs(state_dir, exist_ok=True)
+        if os.path.exists(path):
+            with open(path) as fh:
+                prev = json.load(fh)
+            last = prev["t"][-1] if prev["t"] else None
+            if last is not None and all(os.path.exists(saved(k, last)) for k in states):
+                out, t = prev, last
+                states = {k: np.load(saved(k, last)) for k in states}
+                print(f"{case}: resuming at t={t}", flush=True)
     t0 = time.time()
     while True:
-        out["t"].append(t)
-        for k, H in states.items():
-            out["obs"][k].append(observables(H))
-            if t in SAMPLE_STEPS:
-                out["samples"][k][str(t)] = [[float(H[f, z, y, x]) for f in range(11)] for (z, y, x) in nodes]
-        with open(path + ".tmp", "w") as fh:
-            json.dump(out, fh)
-        os.replace(path + ".tmp", path)
+        if not out["t"] or out["t"][-1] != t:
+            out["t"].append(t)
+            for k, H in states.items():
+                out["obs"][k].append(observables(H))
+                if t in SAMPLE_STEPS:
+                    out["samples"][k][str(t)] = [[float(H[f, z, y, x]) for f in range(11)] for (z, y, x) in nodes]
+            if state_dir:
+                for k, H in states.items():
+                    np.save(saved(k, t), H)
+            with open(path + ".tmp", "w") as fh:
+                json.dump(out, fh)
+            os.replace(path + ".tmp", path)
+            if state_dir and t >= EVERY:
+                for k in states:
+                    if os.path.exists(saved(k, t - EVERY)):
+                        os.remove(saved(k, t - EVERY))
         print(f"{case}: t={t} ({time.time() - t0:.0f} s)", flush=True)
         if t >= STEPS:
             break
@@ -132,5 +155,8 @@ def run(case: str) -> str:
 
 
 if __name__ == "__main__":
-    for c in (sys.argv[1:] or ["c3_recipe_128", "head_on_128"]):
-        print(run(c), flush=True)
+    args, state_dir = sys.argv[1:], None
+    if args[:1] == ["--state-dir"]:
+        state_dir, args = args[1], args[2:]
+    for c in (args or ["c3_recipe_128", "head_on_128"]):
+        print(run(c, state_dir), flush=True)
