@@ -129,16 +129,29 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(
     const int lx = tid % TX, ly = tid / TX;
     const bool active = (x0 + lx < g.nx) && (y0 + ly < g.ny);
     const int h0 = (ly + 1) * HX + (lx + 1);
-    const bool has_ring = tid < RING;
-    int hr;
-    {
-        const int m = tid;
-        int hx, hy;
-        if (m < HX) { hx = m; hy = 0; }
-        else if (m < 2 * HX) { hx = m - HX; hy = HY - 1; }
-        else if (m < 2 * HX + TY) { hx = 0; hy = 1 + (m - 2 * HX); }
-        else { hx = HX - 1; hy = 1 + (m - 2 * HX - TY); }
-        hr = hy * HX + hx;
+    // Halo ring node of this thread.  The ring rows (x inside the tile) take
+    // threads [0, 2 TX), the ring columns (corners included) the threads from
+    // the next multiple of 64 on, so that a wave holds ring nodes of one or two
+    // orientations.  A ring node y + c_i is gathered from only by directions i
+    // that point out of the tile across its side (c_y = -1 for the row above,
+    // +1 below, c_x = -1 for the column on the left, +1 on the right), so it
+    // publishes e_i for those alone (5 of 19 for D3Q19, 9 of 27 for D3Q27; a
+    // corner publishes those of its column, which include the ones it sends).
+    constexpr int ROWS = 2 * TX, CB = (ROWS + 63) / 64 * 64, COLS = 2 * HY;
+    static_assert(ROWS + COLS == RING && CB + COLS <= NT, "ring threads must fit the workgroup");
+    const bool ring_row = tid < ROWS;
+    const bool ring_col = tid >= CB && tid < CB + COLS;
+    const bool has_ring = ring_row || ring_col;
+    int hr = 0, ring_side = 0;  // 0: above, 1: below, 2: left, 3: right
+    if (ring_row) {
+        const bool above = tid < TX;
+        hr = (above ? 0 : HY - 1) * HX + 1 + (above ? tid : tid - TX);
+        ring_side = above ? 0 : 1;
+    } else if (ring_col) {
+        const int m = tid - CB;
+        const bool left = m < HY;
+        hr = (left ? m : m - HY) * HX + (left ? 0 : HX - 1);
+        ring_side = left ? 2 : 3;
     }
     auto xy_of = [&](int h) -> int64_t {
         return (int64_t)wrap_coord(x0 - 1 + h % HX, g.nx) + (int64_t)g.nx * wrap_coord(y0 - 1 + h / HX, g.ny);
@@ -169,13 +182,19 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(
         }
     };
 
-    // e_i and d of one co-state node into LDS slot h.
-    auto publish = [&](const R *l, int h) {
+    // e_i and d of one co-state node into LDS slot h; SIDE < 0 publishes
+    // every direction, SIDE = 0..3 only those leaving the tile across that
+    // side of the ring.
+    auto publish = [&](auto side, const R *l, int h) {
+        constexpr int SIDE = decltype(side)::value;
         lds_d[h] = l[0] - l[1];
         const R gbar = R(0.5) * (l[0] + l[1]);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int cx = Lattice<Q>::cx(i), cy = Lattice<Q>::cy(i), cz = Lattice<Q>::cz(i);
+            if ((SIDE == 0 && cy != -1) || (SIDE == 1 && cy != 1) || (SIDE == 2 && cx != -1) ||
+                (SIDE == 3 && cx != 1))
+                continue;
             R e = gbar;
             if (cx) e = cx > 0 ? e + l[2] : e - l[2];
             if (cy) e = cy > 0 ? e + l[3] : e - l[3];
@@ -348,8 +367,15 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(
 
     auto plane_step = [&](int p, R *own, R *ring) {
         write_phi(p + 1);
-        publish(own, h0);
-        if (has_ring) publish(ring, hr);
+        publish(std::integral_constant<int, -1>(), own, h0);
+        if (has_ring) {
+            switch (ring_side) {
+            case 0: publish(std::integral_constant<int, 0>(), ring, hr); break;
+            case 1: publish(std::integral_constant<int, 1>(), ring, hr); break;
+            case 2: publish(std::integral_constant<int, 2>(), ring, hr); break;
+            default: publish(std::integral_constant<int, 3>(), ring, hr); break;
+            }
+        }
         __syncthreads();
         if (p + 2 <= z_end) fetch(p + 2, own, ring);
         gather_layer(std::integral_constant<int, -1>());
