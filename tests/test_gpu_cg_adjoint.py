@@ -170,3 +170,48 @@ def test_cg_tau_gradient_finite_difference(mods, oracle):
     fd = (vals[0] - vals[1]) / (2 * h)
     _say(f"  dL/dtau adjoint {gt:.10e} central difference {fd:.10e}")
     assert abs(gt - fd) <= 1e-6 * abs(fd)
+
+
+def test_full_size_adjoint_step_sampled(mods, oracle):
+    """The reverse step on the 512 x 256 x 256 droplet box in the launch
+    configuration the benchmark times (the state after 10 FP32 steps of the
+    two-drop collision, a random co-state), at sampled nodes: interfaces,
+    drop cores, the carrier, tile and z-chunk edges of both passes, the
+    periodic wrap.  lam(t) at a node depends on the state and on lam(t+1)
+    within radius 2 (the colour gradient's phase field and the phase-field
+    chain of its co-state), so the oracle's reverse step on the periodic 7^3
+    window around the node gives the node's exact value."""
+    LBM, _ = mods
+    nz, ny, nx = 256, 256, 512
+    _say(f"two-component adjoint step full size {(nz, ny, nx)} FP32, sampled nodes")
+    r1, r2, u = I.droplet_collision_512()
+    sim = LBM((nx, ny, nz), 19, 0.8, species=2, storage="f32", sigma=SIGMA, beta=BETA)
+    sim.set_equilibrium(torch.from_numpy(np.stack([r1, r2])).cuda(), torch.from_numpy(u).cuda())
+    del r1, r2, u
+    sim.step(10)
+    H = sim.get_moments(torch.float32)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(40)
+    lam = torch.randn(H.shape, generator=gen, device="cuda", dtype=torch.float32)
+    lo = torch.empty_like(lam)
+    sim.adjoint_step(H, lam, lo)
+    torch.cuda.synchronize()
+    nodes = [(128, 118, 136), (128, 118, 216), (128, 158, 176), (128, 118, 176), (128, 138, 296), (128, 138, 376),
+             (128, 98, 336), (128, 128, 256), (0, 0, 0), (255, 255, 511), (63, 3, 63), (64, 4, 64),
+             (127, 7, 127), (128, 8, 128), (191, 255, 0), (192, 0, 511), (128, 119, 137), (129, 117, 215),
+             (100, 128, 175), (156, 118, 176), (128, 79, 176), (128, 139, 297)]
+    R = 3
+    got, ref = [], []
+    for z, y, x in nodes:
+        idx = [torch.tensor([(c + d) % n for d in range(-R, R + 1)], device="cuda") for c, n in ((z, nz), (y, ny),
+                                                                                                   (x, nx))]
+        win = lambda A: A.index_select(1, idx[0]).index_select(2, idx[1]).index_select(3, idx[2]).double().cpu()
+        Hw, Lw = win(H).numpy(), win(lam).numpy()
+        r, _ = oracle.cg_adjoint_step(np.ascontiguousarray(Hw), np.ascontiguousarray(Lw), 19, 0.8, SIGMA, BETA)
+        ref.append(r[:, R, R, R])
+        got.append(lo[:, z, y, x].double().cpu().numpy())
+    sim.close()
+    got, ref = np.array(got), np.array(ref)
+    err = np.abs(got - ref).max(axis=0) / np.abs(ref).max()
+    _say(f"  rel err per field over {len(nodes)} nodes {err}")
+    assert err.max() <= 1000 * 2.0 ** -24

@@ -126,3 +126,29 @@ def test_split_two_species_equals_fused_and_oracle(oracle, q, storage, tol, nc_A
     elem = 8 if storage == "f64" else 4
     assert mem_f[1] == 22 * elem * N and mem_s[1] == (52 if nc_A else 49) * elem * N
     assert mem_s[0] == mem_f[0] + 4 * elem * N
+
+
+@pytest.mark.parametrize("nc_A", [0.0, 0.01])
+def test_split_two_species_full_size_equals_fused(nc_A):
+    """The 512 x 256 x 256 two-component box in the launch configuration the
+    benchmark times, two drops of radius 40 three nodes apart (so that the
+    near-contact force acts), 4 steps: the split schedule equals the fused
+    step bit for bit."""
+    from paper_2301_01622_amd.lbm import LBM
+    nz, ny, nx = 256, 256, 512
+    _say(f"two-species split full size {(nz, ny, nx)} FP32 nc_A={nc_A} 4 steps")
+    r1, r2, u = I.droplets((nz, ny, nx), centres=[(214.5, 127.6, 128.3), (297.5, 128.4, 127.8)], radius=40.0,
+                           velocities=[(0.02, 0.0, 0.0), (-0.02, 0.0, 0.0)])
+    prim, uu = torch.from_numpy(np.stack([r1, r2])).cuda(), torch.from_numpy(u).cuda()
+    del r1, r2, u
+    out = []
+    for split in (True, False):
+        sim = LBM((nx, ny, nz), 19, 0.8, species=2, storage="f32", sigma=0.01, beta=0.7, split=split, nc_A=nc_A,
+                  nc_hmax=4 if nc_A else 0)
+        sim.set_equilibrium(prim, uu)
+        sim.step(4)
+        out.append(sim.get_moments(torch.float32))
+        sim.close()
+    same = torch.equal(out[0], out[1])
+    _say(f"  bitwise equal: {same}; max |split - fused| {float((out[0] - out[1]).abs().max()):.3e}")
+    assert same
