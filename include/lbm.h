@@ -156,7 +156,8 @@ void lbm_default_opts(lbm_opts *opts);
  *   lattice : 19 or 27
  *   tau     : BGK relaxation time (Eq. 7, omega = 1/tau), > 1/2
  *   species : 1, or 2 for the colour-gradient mixture (moment scheme with
- *             FP32/FP64 storage, or population scheme with FP32 storage).  Two species: phase field
+ *             FP32/FP64 storage and one stored xy-plane of the 11 fields below
+ *             2 GiB, or population scheme with FP32 storage).  Two species: phase field
  *             phi = (rho1 - rho2)/rho, colour gradient
  *             G = (1/c_s^2) sum_i w_i c_i phi(x + c_i), perturbation with second
  *             moment (A/9)(G G - |G|^2 I)/D, A = 9 sigma/(2 tau), recolouring

@@ -243,6 +243,11 @@ static int validate(lbm_grid grid, int lattice, int species, const lbm_opts &o, 
         if (scaled ? std::frexp(o.s_pi, &e2) != 0.5 : o.s_pi != 1.0) return LBM_EINVAL;
     }
     if (species == 2 && o.scheme == LBM_SCHEME_POPULATION && o.storage != LBM_STORE_F32) return LBM_EINVAL;
+    // The two-component moment step addresses one stored z-plane (11 fields)
+    // per buffer descriptor: at most 2 GiB.
+    if (species == 2 && o.scheme == LBM_SCHEME_MOMENT &&
+        lbm::moment_layout(grid.nx, grid.ny, 11).plane * (int64_t)storage_bytes(o.storage) >= ((int64_t)1 << 31))
+        return LBM_EINVAL;
 
     // Near-contact force: two species only, finite strength, 1..32 probes;
     // its per-node passes launch one block row per z-plane and 4 rows of y

@@ -31,6 +31,39 @@
 namespace lbm {
 namespace {
 
+// Buffer addressing of one z-plane: the descriptor (base and byte range of
+// the plane) sits in scalar registers, the node's byte offset in one 32-bit
+// vector register and the field offset in a scalar one, so no 64-bit address
+// arithmetic runs in the vector unit (the stored fields lie 4 KiB apart,
+// beyond the immediate offset of global accesses).  Accesses beyond the range
+// read 0 and write nothing.  A plane must stay below 2 GiB (lbm_create checks
+// it for two species).
+template <class R>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_buf(const R *p, int64_t elems)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<R *>(p), (short)0, (int)(elems * (int64_t)sizeof(R)),
+                                             0x00020000);
+}
+template <class R>
+__device__ __forceinline__ R buf_load(__amdgpu_buffer_rsrc_t rs, uint32_t vo, int so)
+{
+    if constexpr (sizeof(R) == 4)
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0));
+    else
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0));
+}
+// Nontemporal store (cache-policy bit 1), as the other kernels' stores.
+template <class R>
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t rs, uint32_t vo, int so, R v)
+{
+    if constexpr (sizeof(R) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, vo, so, 2);
+    } else {
+        using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0u, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), rs, vo, so, 2);
+    }
+}
+
 template <class R>
 struct CgAcc {
     MomentAcc<R> m;
@@ -204,23 +237,40 @@ __global__ __launch_bounds__(TX *TY, WPE) void k_cg_tile(const R *__restrict__ i
     };
     PlaneRegs pa, pb;
     auto zwrap = [&](int p) { return p < 0 ? p + g.nz : (p >= g.nz ? p - g.nz : p); };
+    // Byte offsets within one plane: the stored state (fields kBlock apart)
+    // and the public-layout arrays (one descriptor per field).
+    constexpr int FB = kBlock * (int)sizeof(R);
+    const uint32_t own_vo = (uint32_t)own_xy * (uint32_t)sizeof(R);
+    const uint32_t ring_vo = (uint32_t)ring_xy * (uint32_t)sizeof(R);
+    const uint32_t outer_vo = (uint32_t)outer_xy * (uint32_t)sizeof(R);
+    const uint32_t own_lvo = (uint32_t)own_lin * (uint32_t)sizeof(R);
+    const uint32_t ring_lvo = (uint32_t)ring_lin * (uint32_t)sizeof(R);
+    const uint32_t dst_vo = active ? (uint32_t)g.lay.xy(x0 + lx, y0 + ly) * (uint32_t)sizeof(R) : 0u;
+    const uint32_t dst_lvo = active ? (uint32_t)((x0 + lx) + g.nx * (y0 + ly)) * (uint32_t)sizeof(R) : 0u;
     auto fetch = [&](int p, PlaneRegs &r) {
-        const int64_t zo = (int64_t)zwrap(p) * plane;
-        load_moments<R, 11>(in, kBlock, own_xy + zo, r.own);
-        if (has_ring) load_moments<R, 11>(in, kBlock, ring_xy + zo, r.ring);
+        const __amdgpu_buffer_rsrc_t rs = plane_buf(in + (int64_t)zwrap(p) * plane, plane);
+#pragma unroll
+        for (int k = 0; k < 11; ++k) r.own.v[k] = buf_load<R>(rs, own_vo, k * FB);
+        if (has_ring) {
+#pragma unroll
+            for (int k = 0; k < 11; ++k) r.ring.v[k] = buf_load<R>(rs, ring_vo, k * FB);
+        }
         if (!COLL && has_outer) {
-            r.outer_dr = in[outer_xy + zo];
-            r.outer_r1 = in[kBlock + outer_xy + zo];
+            r.outer_dr = buf_load<R>(rs, outer_vo, 0);
+            r.outer_r1 = buf_load<R>(rs, outer_vo, FB);
         }
         if (VEC3) {
             const int64_t zl = (int64_t)zwrap(p) * plane_lin;
-            r.fox = frc[own_lin + zl];
-            r.foy = frc[g.N + own_lin + zl];
-            r.foz = frc[2 * g.N + own_lin + zl];
+            const __amdgpu_buffer_rsrc_t fx = plane_buf(frc + zl, plane_lin);
+            const __amdgpu_buffer_rsrc_t fy = plane_buf(frc + g.N + zl, plane_lin);
+            const __amdgpu_buffer_rsrc_t fz = plane_buf(frc + 2 * g.N + zl, plane_lin);
+            r.fox = buf_load<R>(fx, own_lvo, 0);
+            r.foy = buf_load<R>(fy, own_lvo, 0);
+            r.foz = buf_load<R>(fz, own_lvo, 0);
             if (has_ring) {
-                r.frx = frc[ring_lin + zl];
-                r.fry = frc[g.N + ring_lin + zl];
-                r.frz = frc[2 * g.N + ring_lin + zl];
+                r.frx = buf_load<R>(fx, ring_lvo, 0);
+                r.fry = buf_load<R>(fy, ring_lvo, 0);
+                r.frz = buf_load<R>(fz, ring_lvo, 0);
             }
         }
     };
@@ -427,21 +477,23 @@ __global__ __launch_bounds__(TX *TY, WPE) void k_cg_tile(const R *__restrict__ i
 
         const int d = p - 1;
         if (d >= z0 && active) {
-            const int64_t o = g.lay.xy(x0 + lx, y0 + ly) + (int64_t)d * plane;
+            const __amdgpu_buffer_rsrc_t ws = plane_buf(out + (int64_t)d * plane, plane);
             const MomentAcc<R> &a = acc[0].m;
             const R m3 = R(-1.0 / 3.0);
-            store_out(out + o, a.r);
-            store_out(out + kBlock + o, acc[0].rho1);
-            store_out(out + 2 * kBlock + o, a.jx);
-            store_out(out + 3 * kBlock + o, a.jy);
-            store_out(out + 4 * kBlock + o, a.jz);
-            store_out(out + 5 * kBlock + o, fma_(m3, a.r, a.mxx));
-            store_out(out + 6 * kBlock + o, fma_(m3, a.r, a.myy));
-            store_out(out + 7 * kBlock + o, fma_(m3, a.r, a.mzz));
-            store_out(out + 8 * kBlock + o, a.mxy);
-            store_out(out + 9 * kBlock + o, a.mxz);
-            store_out(out + 10 * kBlock + o, a.myz);
-            if (FORCE) phi_out[(x0 + lx) + (int64_t)g.nx * ((y0 + ly) + (int64_t)g.ny * d)] = phi_of(a.r, acc[0].rho1);
+            buf_store<R>(ws, dst_vo, 0, a.r);
+            buf_store<R>(ws, dst_vo, FB, acc[0].rho1);
+            buf_store<R>(ws, dst_vo, 2 * FB, a.jx);
+            buf_store<R>(ws, dst_vo, 3 * FB, a.jy);
+            buf_store<R>(ws, dst_vo, 4 * FB, a.jz);
+            buf_store<R>(ws, dst_vo, 5 * FB, fma_(m3, a.r, a.mxx));
+            buf_store<R>(ws, dst_vo, 6 * FB, fma_(m3, a.r, a.myy));
+            buf_store<R>(ws, dst_vo, 7 * FB, fma_(m3, a.r, a.mzz));
+            buf_store<R>(ws, dst_vo, 8 * FB, a.mxy);
+            buf_store<R>(ws, dst_vo, 9 * FB, a.mxz);
+            buf_store<R>(ws, dst_vo, 10 * FB, a.myz);
+            if (FORCE)
+                buf_store<R>(plane_buf(phi_out + (int64_t)d * plane_lin, plane_lin), dst_lvo, 0,
+                             phi_of(a.r, acc[0].rho1));
         }
         acc[0] = acc[1];
         acc[1] = acc[2];
