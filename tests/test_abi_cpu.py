@@ -147,6 +147,24 @@ def test_two_step_sweeps_need_planes_below_2_gib():
     assert not ctx.value
 
 
+def test_two_species_moment_contexts_need_planes_below_2_gib():
+    """The two-component moment step addresses one stored xy-plane of its 11
+    fields per buffer descriptor: 4096 x 4096 FP32 nodes (0.69 GiB) are
+    accepted by the validation (without a GPU the create then fails for want
+    of a device), 8192 x 8192 (2.75 GiB) are refused before any device work."""
+    lib = _lib.load()
+    opts = _lib.Opts()
+    lib.lbm_default_opts(ctypes.byref(opts))
+    ctx = ctypes.c_void_p(123)
+    rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(8192, 8192, 3), 19, 0.8, 2, ctypes.byref(opts))
+    assert rc == _lib.LBM_EINVAL
+    assert not ctx.value
+    rc = lib.lbm_create(ctypes.byref(ctx), _lib.Grid(4096, 4096, 3), 19, 0.8, 2, ctypes.byref(opts))
+    assert rc != _lib.LBM_EINVAL
+    if rc == 0:  # a GPU is present
+        lib.lbm_destroy(ctx)
+
+
 @pytest.mark.parametrize("species,scheme,storage,s_pi", [
     (1, 0, 1, 2.0),      # FP32 storage keeps S unscaled: only 0 or 1
     (1, 0, 0, 1024.0),   # FP64 likewise
