@@ -132,8 +132,15 @@ struct SlotLayout {
 // perturbation, j + F under a force) and frc the interface normal n (three
 // arrays of N values); the step then only reconstructs, recolours, pulls and
 // sums, with the same arithmetic per node as the fused step.
-template <int Q, class R, int TX, int TY, bool FORCE, int WPE, bool COLL = false>
-__global__ __launch_bounds__(TX *TY, WPE) void k_cg_tile(const R *__restrict__ in, R *__restrict__ out, TileGrid g,
+// Threads of a workgroup: one per interior node; with SR (separate ring
+// threads) the halo ring's nodes get threads of their own after them (rows,
+// then columns, each from a multiple of 64), so that no thread handles two
+// nodes.
+template <int TX, int TY, bool SR>
+constexpr int kCgThreads = SR ? TX * TY + (2 * TX + 63) / 64 * 64 + (2 * (TY + 2) + 63) / 64 * 64 : TX * TY;
+
+template <int Q, class R, int TX, int TY, bool FORCE, int WPE, bool COLL = false, bool SR = false>
+__global__ __launch_bounds__((kCgThreads<TX, TY, SR>), WPE) void k_cg_tile(const R *__restrict__ in, R *__restrict__ out, TileGrid g,
                                                     R omega, R A9, R beta, const R *__restrict__ frc,
                                                     R *__restrict__ phi_out)
 {
@@ -165,8 +172,9 @@ __global__ __launch_bounds__(TX *TY, WPE) void k_cg_tile(const R *__restrict__ i
     const int64_t plane = g.lay.plane;  // stored elements per z-plane
 
     const int tid = threadIdx.x;
-    const int lx = tid % TX, ly = tid / TX;
-    const bool active = (x0 + lx < g.nx) && (y0 + ly < g.ny);
+    const bool interior = !SR || tid < NT;
+    const int lx = tid % TX, ly = interior ? tid / TX : 0;
+    const bool active = interior && (x0 + lx < g.nx) && (y0 + ly < g.ny);
     const int h0 = (ly + 1) * SX + (lx + 1);
 
     // Radius-1 ring node of this thread (source region coordinates).  The
@@ -176,15 +184,16 @@ __global__ __launch_bounds__(TX *TY, WPE) void k_cg_tile(const R *__restrict__ i
     // nodes of one orientation only.  A ring node sends into the tile only
     // the directions with c_y = d (rows) or c_x = d (columns), d its inward
     // sign.
-    constexpr int ROWS = 2 * TX, CB = (ROWS + 63) / 64 * 64, COLS = 2 * SY;
-    static_assert(ROWS + COLS == RING && CB + COLS <= NT, "ring threads must fit the workgroup");
-    const bool ring_row = tid < ROWS;
+    constexpr int R0 = SR ? NT : 0;  // first ring thread
+    constexpr int ROWS = 2 * TX, CB = R0 + (ROWS + 63) / 64 * 64, COLS = 2 * SY;
+    static_assert(ROWS + COLS == RING && CB + COLS <= kCgThreads<TX, TY, SR>, "ring threads must fit the workgroup");
+    const bool ring_row = tid >= R0 && tid < R0 + ROWS;
     const bool ring_col = tid >= CB && tid < CB + COLS;
     const bool has_ring = ring_row || ring_col;
     int hr = 0, dsign = 1;
     if (ring_row) {
-        const bool top = tid < TX;
-        hr = (top ? 0 : SY - 1) * SX + 1 + (top ? tid : tid - TX);
+        const bool top = tid - R0 < TX;
+        hr = (top ? 0 : SY - 1) * SX + 1 + (top ? tid - R0 : tid - R0 - TX);
         dsign = top ? 1 : -1;
     } else if (ring_col) {
         const int m = tid - CB;
@@ -192,11 +201,13 @@ __global__ __launch_bounds__(TX *TY, WPE) void k_cg_tile(const R *__restrict__ i
         hr = (left ? m : m - SY) * SX + (left ? 0 : SX - 1);
         dsign = left ? 1 : -1;
     }
-    // Radius-2 ring node of this thread (phase-field region coordinates).
-    const bool has_outer = tid < OUTER;
+    // Radius-2 ring node of this thread (phase-field region coordinates);
+    // with SR on the ring threads.
+    static_assert(!SR || OUTER <= kCgThreads<TX, TY, SR> - NT, "outer ring must fit the ring threads");
+    const bool has_outer = tid >= R0 && tid - R0 < OUTER;
     int ko;
     {
-        const int m = tid;
+        const int m = tid - R0;
         int kx, ky;
         if (m < FX) { kx = m; ky = 0; }
         else if (m < 2 * FX) { kx = m - FX; ky = FY - 1; }
@@ -247,11 +258,16 @@ __global__ __launch_bounds__(TX *TY, WPE) void k_cg_tile(const R *__restrict__ i
     const uint32_t ring_lvo = (uint32_t)ring_lin * (uint32_t)sizeof(R);
     const uint32_t dst_vo = active ? (uint32_t)g.lay.xy(x0 + lx, y0 + ly) * (uint32_t)sizeof(R) : 0u;
     const uint32_t dst_lvo = active ? (uint32_t)((x0 + lx) + g.nx * (y0 + ly)) * (uint32_t)sizeof(R) : 0u;
+    // With SR a ring thread keeps its node in the `own` registers.
+    const uint32_t node_vo = SR && !interior ? ring_vo : own_vo;
+    const uint32_t node_lvo = SR && !interior ? ring_lvo : own_lvo;
     auto fetch = [&](int p, PlaneRegs &r) {
         const __amdgpu_buffer_rsrc_t rs = plane_buf(in + (int64_t)zwrap(p) * plane, plane);
+        if (!SR || interior || has_ring) {
 #pragma unroll
-        for (int k = 0; k < 11; ++k) r.own.v[k] = buf_load<R>(rs, own_vo, k * FB);
-        if (has_ring) {
+            for (int k = 0; k < 11; ++k) r.own.v[k] = buf_load<R>(rs, node_vo, k * FB);
+        }
+        if (!SR && has_ring) {
 #pragma unroll
             for (int k = 0; k < 11; ++k) r.ring.v[k] = buf_load<R>(rs, ring_vo, k * FB);
         }
@@ -264,10 +280,12 @@ __global__ __launch_bounds__(TX *TY, WPE) void k_cg_tile(const R *__restrict__ i
             const __amdgpu_buffer_rsrc_t fx = plane_buf(frc + zl, plane_lin);
             const __amdgpu_buffer_rsrc_t fy = plane_buf(frc + g.N + zl, plane_lin);
             const __amdgpu_buffer_rsrc_t fz = plane_buf(frc + 2 * g.N + zl, plane_lin);
-            r.fox = buf_load<R>(fx, own_lvo, 0);
-            r.foy = buf_load<R>(fy, own_lvo, 0);
-            r.foz = buf_load<R>(fz, own_lvo, 0);
-            if (has_ring) {
+            if (!SR || interior || has_ring) {
+                r.fox = buf_load<R>(fx, node_lvo, 0);
+                r.foy = buf_load<R>(fy, node_lvo, 0);
+                r.foz = buf_load<R>(fz, node_lvo, 0);
+            }
+            if (!SR && has_ring) {
                 r.frx = buf_load<R>(fx, ring_lvo, 0);
                 r.fry = buf_load<R>(fy, ring_lvo, 0);
                 r.frz = buf_load<R>(fz, ring_lvo, 0);
@@ -279,8 +297,12 @@ __global__ __launch_bounds__(TX *TY, WPE) void k_cg_tile(const R *__restrict__ i
     auto write_phi = [&](int p, const PlaneRegs &r) {
         if (COLL) return;
         R *ph = lds_phi + slot_of(p) * FN;
-        ph[k_own] = phi_of(r.own.v[0], r.own.v[1]);
-        if (has_ring) ph[k_ring] = phi_of(r.ring.v[0], r.ring.v[1]);
+        if constexpr (SR) {
+            if (interior || has_ring) ph[interior ? k_own : k_ring] = phi_of(r.own.v[0], r.own.v[1]);
+        } else {
+            ph[k_own] = phi_of(r.own.v[0], r.own.v[1]);
+            if (has_ring) ph[k_ring] = phi_of(r.ring.v[0], r.ring.v[1]);
+        }
         if (has_outer) ph[ko] = phi_of(r.outer_dr, r.outer_r1);
     };
 
@@ -461,19 +483,23 @@ __global__ __launch_bounds__(TX *TY, WPE) void k_cg_tile(const R *__restrict__ i
         write_phi(p + 1, nxt);
         __syncthreads();
         R oh[3], of[3];
-        publish(p, cur.own, h0, oh, of, cur.fox, cur.foy, cur.foz);
+        if (interior) publish(p, cur.own, h0, oh, of, cur.fox, cur.foy, cur.foz);
+        const M11 &rv = SR ? cur.own : cur.ring;
+        const R rfx = SR ? cur.fox : cur.frx, rfy = SR ? cur.foy : cur.fry, rfz = SR ? cur.foz : cur.frz;
         if (ring_row) {
-            if (dsign > 0) publish_ring(std::true_type(), Up(), p, cur.ring, hr, cur.frx, cur.fry, cur.frz);
-            else publish_ring(std::true_type(), Down(), p, cur.ring, hr, cur.frx, cur.fry, cur.frz);
+            if (dsign > 0) publish_ring(std::true_type(), Up(), p, rv, hr, rfx, rfy, rfz);
+            else publish_ring(std::true_type(), Down(), p, rv, hr, rfx, rfy, rfz);
         } else if (ring_col) {
-            if (dsign > 0) publish_ring(std::false_type(), Up(), p, cur.ring, hr, cur.frx, cur.fry, cur.frz);
-            else publish_ring(std::false_type(), Down(), p, cur.ring, hr, cur.frx, cur.fry, cur.frz);
+            if (dsign > 0) publish_ring(std::false_type(), Up(), p, rv, hr, rfx, rfy, rfz);
+            else publish_ring(std::false_type(), Down(), p, rv, hr, rfx, rfy, rfz);
         }
         __syncthreads();
         if (p + 2 <= z_end + 1) fetch(p + 2, cur);
-        pull_layer(std::integral_constant<int, -1>(), acc[0], oh[0], of[0]);
-        pull_layer(std::integral_constant<int, 0>(), acc[1], oh[1], of[1]);
-        pull_layer(std::integral_constant<int, 1>(), acc[2], oh[2], of[2]);
+        if (interior) {
+            pull_layer(std::integral_constant<int, -1>(), acc[0], oh[0], of[0]);
+            pull_layer(std::integral_constant<int, 0>(), acc[1], oh[1], of[1]);
+            pull_layer(std::integral_constant<int, 1>(), acc[2], oh[2], of[2]);
+        }
 
         const int d = p - 1;
         if (d >= z0 && active) {
@@ -534,11 +560,12 @@ inline int balanced_zchunk(int nz, int tiles, int slots)
 // Resident workgroups per CU each variant is sized for: WG for the plain
 // step, WGF for the step with the near-contact force, WGC for the streaming
 // pass of the split schedule.
-template <int Q, class R, int TX, int TY, int WG, int WGF, int WGC>
+// SR: the plain step with separate ring threads.
+template <int Q, class R, int TX, int TY, int WG, int WGF, int WGC, bool SR = false>
 hipError_t run(const lbm_ctx *c, const void *in, void *out, bool phi_cached, const void *normal = nullptr)
 {
     // Waves per SIMD the register allocation must leave room for.
-    constexpr int WPE = (TX * TY / 64 * WG + 3) / 4, WPEF = (TX * TY / 64 * WGF + 3) / 4,
+    constexpr int WPE = (kCgThreads<TX, TY, SR> / 64 * WG + 3) / 4, WPEF = (TX * TY / 64 * WGF + 3) / 4,
                   WPEC = (TX * TY / 64 * WGC + 3) / 4;
     auto grid = [&](int wg, TileGrid &g) -> int64_t {
         g.nx = c->nx;
@@ -571,9 +598,9 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out, bool phi_cached, con
                            static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega, (R)(c->A / 9.0),
                            (R)c->beta, static_cast<const R *>(c->scratch_nc), phi);
     } else {
-        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, false, WPE>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
-                           static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega, (R)(c->A / 9.0),
-                           (R)c->beta, nullptr, nullptr);
+        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, false, WPE, false, SR>), dim3((unsigned)blocks),
+                           dim3(kCgThreads<TX, TY, SR>), 0, c->stream, static_cast<const R *>(in),
+                           static_cast<R *>(out), g, (R)c->omega, (R)(c->A / 9.0), (R)c->beta, nullptr, nullptr);
     }
     return hipGetLastError();
 }
@@ -581,19 +608,23 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out, bool phi_cached, con
 } // namespace
 
 // D3Q19 FP32 tiles: 64 x 4 nodes (full 64-wide rows of the stored blocks).
-// The plain step is sized for three resident workgroups per CU (166 VGPRs,
-// no spills; 4-5 % faster than two on 512 x 256 x 256, where each workgroup
-// marches a third of the column).  The step with the near-contact force
-// (194 VGPRs) and the streaming pass of the split schedule (which spills at
-// three) stay at two.  Measured against 32 x 8, 64 x 8, 32 x 16 and 128 x 4
-// tiles and other chunkings; the shape is a compile-time choice (LBM_CG_TX,
-// LBM_CG_TY, LBM_CG_WG, LBM_CG_WGF, LBM_CG_WGC).
+// The plain step gives the halo ring threads of their own (LBM_CG_SR: 448
+// threads, 7 waves, each thread one node, so every wave collides one node per
+// plane; 128 VGPRs without spills) and is sized for two resident workgroups
+// per CU (14 waves; on 512 x 256 x 256 each marches a whole column): 0.725 ->
+// 0.686 ms per step against 256 threads that collide an interior and a ring
+// node each at three workgroups per CU.  The step with the near-contact force
+// (176 VGPRs; 128 would spill) and the streaming pass of the split schedule
+// (slower with ring threads) keep 256 threads at two workgroups per CU.
+// Measured against 32 x 8, 64 x 8, 32 x 16 and 128 x 4 tiles and other
+// chunkings; the shape is a compile-time choice (LBM_CG_TX, LBM_CG_TY,
+// LBM_CG_WG, LBM_CG_WGF, LBM_CG_WGC, LBM_CG_SR).
 #ifndef LBM_CG_TX
 #define LBM_CG_TX 64
 #define LBM_CG_TY 4
 #endif
 #ifndef LBM_CG_WG
-#define LBM_CG_WG 3
+#define LBM_CG_WG 2
 #endif
 #ifndef LBM_CG_WGF
 #define LBM_CG_WGF 2
@@ -601,12 +632,16 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out, bool phi_cached, con
 #ifndef LBM_CG_WGC
 #define LBM_CG_WGC 2
 #endif
+#ifndef LBM_CG_SR
+#define LBM_CG_SR true
+#endif
 
 hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out, bool phi_cached, const void *normal)
 {
     if (c->species != 2) return hipErrorNotSupported;
     if (c->storage == LBM_STORE_F32)
-        return c->q == 19 ? run<19, float, LBM_CG_TX, LBM_CG_TY, LBM_CG_WG, LBM_CG_WGF, LBM_CG_WGC>(c, in, out, phi_cached, normal)
+        return c->q == 19 ? run<19, float, LBM_CG_TX, LBM_CG_TY, LBM_CG_WG, LBM_CG_WGF, LBM_CG_WGC, LBM_CG_SR>(c, in, out, phi_cached,
+                                                                                        normal)
                           : run<27, float, 32, 8, 2, 2, 2>(c, in, out, phi_cached, normal);
     if (c->storage == LBM_STORE_F64)
         return c->q == 19 ? run<19, double, 32, 4, 2, 2, 2>(c, in, out, phi_cached, normal)
