@@ -560,92 +560,95 @@ inline int balanced_zchunk(int nz, int tiles, int slots)
 // Resident workgroups per CU each variant is sized for: WG for the plain
 // step, WGF for the step with the near-contact force, WGC for the streaming
 // pass of the split schedule.
-// SR: the plain step with separate ring threads.
-template <int Q, class R, int TX, int TY, int WG, int WGF, int WGC, bool SR = false>
+// Launch shape of one variant of the step: TY tile rows, WG resident
+// workgroups per CU the z-chunks (and the register allocation) are sized for,
+// SR separate ring threads.
+template <int TY_, int WG_, bool SR_>
+struct CgShape {
+    static constexpr int TY = TY_, WG = WG_;
+    static constexpr bool SR = SR_;
+};
+
+template <int Q, class R, int TX, class SH, bool FORCE, bool COLL>
+hipError_t launch_tile(const lbm_ctx *c, const void *in, void *out, const R *frc, R *phi_out)
+{
+    constexpr int TY = SH::TY, NTH = kCgThreads<TX, TY, SH::SR>;
+    // Waves per SIMD the register allocation must leave room for.
+    constexpr int WPE = (NTH / 64 * SH::WG + 3) / 4;
+    TileGrid g;
+    g.nx = c->nx;
+    g.ny = c->ny;
+    g.nz = c->nz;
+    g.N = c->N;
+    g.lay = c->lay;
+    g.tiles_x = (c->nx + TX - 1) / TX;
+    g.tiles_y = (c->ny + TY - 1) / TY;
+    g.zchunk = balanced_zchunk(c->nz, g.tiles_x * g.tiles_y, 256 * SH::WG);
+    g.chunks = (c->nz + g.zchunk - 1) / g.zchunk;
+    const int64_t blocks = (int64_t)g.tiles_x * g.tiles_y * g.chunks;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, FORCE, WPE, COLL, SH::SR>), dim3((unsigned)blocks), dim3(NTH), 0,
+                       c->stream, static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega,
+                       (R)(c->A / 9.0), (R)c->beta, frc, phi_out);
+    return hipGetLastError();
+}
+
+// P, F, C: shapes of the plain step, the step with the near-contact force and
+// the streaming pass of the split schedule.
+template <int Q, class R, int TX, class P, class F, class C>
 hipError_t run(const lbm_ctx *c, const void *in, void *out, bool phi_cached, const void *normal = nullptr)
 {
-    // Waves per SIMD the register allocation must leave room for.
-    constexpr int WPE = (kCgThreads<TX, TY, SR> / 64 * WG + 3) / 4, WPEF = (TX * TY / 64 * WGF + 3) / 4,
-                  WPEC = (TX * TY / 64 * WGC + 3) / 4;
-    auto grid = [&](int wg, TileGrid &g) -> int64_t {
-        g.nx = c->nx;
-        g.ny = c->ny;
-        g.nz = c->nz;
-        g.N = c->N;
-        g.lay = c->lay;
-        g.tiles_x = (c->nx + TX - 1) / TX;
-        g.tiles_y = (c->ny + TY - 1) / TY;
-        g.zchunk = balanced_zchunk(c->nz, g.tiles_x * g.tiles_y, 256 * wg);
-        g.chunks = (c->nz + g.zchunk - 1) / g.zchunk;
-        return (int64_t)g.tiles_x * g.tiles_y * g.chunks;
-    };
-    TileGrid g;
-    const bool force = c->nc_A != 0.0 && !normal;
-    const int64_t blocks = grid(normal ? WGC : force ? WGF : WG, g);
-    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    if (normal) {
-        // Streaming pass of the split schedule.
-        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, false, WPEC, true>), dim3((unsigned)blocks), dim3(TX * TY), 0,
-                           c->stream, static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega,
-                           (R)(c->A / 9.0), (R)c->beta, static_cast<const R *>(normal), nullptr);
-    } else if (force) {
+    if (normal)  // streaming pass of the split schedule
+        return launch_tile<Q, R, TX, C, false, true>(c, in, out, static_cast<const R *>(normal), nullptr);
+    if (c->nc_A != 0.0) {
         // Near-contact force of this state first (into the context's scratch:
         // F, then the phase field, reused when the previous step wrote it).
         R *phi = static_cast<R *>(c->scratch_nc) + 3 * c->N;
         hipError_t e = phi_cached ? launch_nc_force(c, nullptr, phi) : launch_nc_force(c, in, nullptr);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, true, WPEF>), dim3((unsigned)blocks), dim3(TX * TY), 0, c->stream,
-                           static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega, (R)(c->A / 9.0),
-                           (R)c->beta, static_cast<const R *>(c->scratch_nc), phi);
-    } else {
-        hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, false, WPE, false, SR>), dim3((unsigned)blocks),
-                           dim3(kCgThreads<TX, TY, SR>), 0, c->stream, static_cast<const R *>(in),
-                           static_cast<R *>(out), g, (R)c->omega, (R)(c->A / 9.0), (R)c->beta, nullptr, nullptr);
+        return launch_tile<Q, R, TX, F, true, false>(c, in, out, static_cast<const R *>(c->scratch_nc), phi);
     }
-    return hipGetLastError();
+    return launch_tile<Q, R, TX, P, false, false>(c, in, out, nullptr, nullptr);
 }
 
 } // namespace
 
 // D3Q19 FP32 tiles: 64 x 4 nodes (full 64-wide rows of the stored blocks).
-// The plain step gives the halo ring threads of their own (LBM_CG_SR: 448
-// threads, 7 waves, each thread one node, so every wave collides one node per
-// plane; 128 VGPRs without spills) and is sized for two resident workgroups
-// per CU (14 waves; on 512 x 256 x 256 each marches a whole column): 0.725 ->
-// 0.686 ms per step against 256 threads that collide an interior and a ring
-// node each at three workgroups per CU.  The step with the near-contact force
-// (176 VGPRs; 128 would spill) and the streaming pass of the split schedule
+// The plain step gives the halo ring threads of their own (448 threads, 7
+// waves, each thread one node, so every wave collides one node per plane; 128
+// VGPRs without spills) and is sized for two resident workgroups per CU (14
+// waves; on 512 x 256 x 256 each marches a whole column): 0.725 -> 0.686 ms
+// per step against 256 threads that collide an interior and a ring node each
+// at three workgroups per CU.  The step with the near-contact force (176
+// VGPRs; 128 would spill) and the streaming pass of the split schedule
 // (slower with ring threads) keep 256 threads at two workgroups per CU.
-// Measured against 32 x 8, 64 x 8, 32 x 16 and 128 x 4 tiles and other
-// chunkings; the shape is a compile-time choice (LBM_CG_TX, LBM_CG_TY,
-// LBM_CG_WG, LBM_CG_WGF, LBM_CG_WGC, LBM_CG_SR).
-#ifndef LBM_CG_TX
-#define LBM_CG_TX 64
-#define LBM_CG_TY 4
+// 64 x 8 tiles with ring threads (11 waves, one workgroup per CU) ran 7 %
+// slower for the plain step and 6 % for the force variant on 512 x 256 x 256
+// (4 % faster for the latter on 128^3).  Also measured against 32 x 8, 32 x 16
+// and 128 x 4 tiles and other chunkings; each shape is a compile-time choice
+// (LBM_CG_P, LBM_CG_F, LBM_CG_C: tile rows, workgroups per CU, ring threads).
+#ifndef LBM_CG_P
+#define LBM_CG_P 4, 2, true
 #endif
-#ifndef LBM_CG_WG
-#define LBM_CG_WG 2
+#ifndef LBM_CG_F
+#define LBM_CG_F 4, 2, false
 #endif
-#ifndef LBM_CG_WGF
-#define LBM_CG_WGF 2
-#endif
-#ifndef LBM_CG_WGC
-#define LBM_CG_WGC 2
-#endif
-#ifndef LBM_CG_SR
-#define LBM_CG_SR true
+#ifndef LBM_CG_C
+#define LBM_CG_C 4, 2, false
 #endif
 
 hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out, bool phi_cached, const void *normal)
 {
     if (c->species != 2) return hipErrorNotSupported;
+    using S2 = CgShape<4, 2, false>;
+    using S8 = CgShape<8, 2, false>;
     if (c->storage == LBM_STORE_F32)
-        return c->q == 19 ? run<19, float, LBM_CG_TX, LBM_CG_TY, LBM_CG_WG, LBM_CG_WGF, LBM_CG_WGC, LBM_CG_SR>(c, in, out, phi_cached,
-                                                                                        normal)
-                          : run<27, float, 32, 8, 2, 2, 2>(c, in, out, phi_cached, normal);
+        return c->q == 19 ? run<19, float, 64, CgShape<LBM_CG_P>, CgShape<LBM_CG_F>, CgShape<LBM_CG_C>>(
+                                c, in, out, phi_cached, normal)
+                          : run<27, float, 32, S8, S8, S8>(c, in, out, phi_cached, normal);
     if (c->storage == LBM_STORE_F64)
-        return c->q == 19 ? run<19, double, 32, 4, 2, 2, 2>(c, in, out, phi_cached, normal)
-                          : run<27, double, 32, 4, 2, 2, 2>(c, in, out, phi_cached, normal);
+        return c->q == 19 ? run<19, double, 32, S2, S2, S2>(c, in, out, phi_cached, normal)
+                          : run<27, double, 32, S2, S2, S2>(c, in, out, phi_cached, normal);
     return hipErrorInvalidValue;
 }
 
