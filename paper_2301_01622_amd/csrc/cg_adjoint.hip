@@ -168,18 +168,21 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(
     auto zoff = [&](int p) -> int64_t { return (int64_t)zs_of(p) * plane; };
     auto ring_slot = [&](int p) { return (p - z0 + 4) & 3; };
 
-    // phi of plane p for this thread's nodes (from the stored dr and rho1).
-    auto write_phi = [&](int p) {
+    // phi of plane p for this thread's nodes (from the stored dr and rho1):
+    // the loads (one plane ahead of their use), then the LDS writes.
+    auto load_phi = [&](int p, R *v) {
         const int64_t zo = (int64_t)zs_of(p) * g.lay.plane;
-        R *ph = lds_phi + ring_slot(p) * HN;
-        {
-            const R dr = state[own_sxy + zo], r1 = state[kBlock + own_sxy + zo];
-            ph[h0] = fma_(R(2) * r1, reciprocal<R>(R(1) + dr), R(-1));
-        }
+        v[0] = state[own_sxy + zo];
+        v[1] = state[kBlock + own_sxy + zo];
         if (has_ring) {
-            const R dr = state[ring_sxy + zo], r1 = state[kBlock + ring_sxy + zo];
-            ph[hr] = fma_(R(2) * r1, reciprocal<R>(R(1) + dr), R(-1));
+            v[2] = state[ring_sxy + zo];
+            v[3] = state[kBlock + ring_sxy + zo];
         }
+    };
+    auto store_phi = [&](int p, const R *v) {
+        R *ph = lds_phi + ring_slot(p) * HN;
+        ph[h0] = fma_(R(2) * v[1], reciprocal<R>(R(1) + v[0]), R(-1));
+        if (has_ring) ph[hr] = fma_(R(2) * v[3], reciprocal<R>(R(1) + v[2]), R(-1));
     };
 
     // e_i and d of one co-state node into LDS slot h; SIDE < 0 publishes
@@ -245,18 +248,25 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(
         a.vz += vz;
     };
 
-    auto finish = [&](int dpl) {
+    // The node's own state of plane dpl, loaded a plane step before finish()
+    // uses it.
+    auto load_own = [&](int dpl, R *v) {
+        const int64_t so = g.lay.xy(x0 + lx, y0 + ly) + (int64_t)dpl * g.lay.plane;
+#pragma unroll
+        for (int k = 0; k < 11; ++k) v[k] = state[k * kBlock + so];
+    };
+    auto finish = [&](int dpl, const R *st) {
         const int64_t so = g.lay.xy(x0 + lx, y0 + ly) + (int64_t)dpl * g.lay.plane;    // stored
         const int64_t op = (int64_t)(x0 + lx) + (int64_t)g.nx * (y0 + ly) + (int64_t)dpl * plane;  // public
         const int64_t o = LSTORED ? so : op;  // co-states
         const int64_t LF = LSTORED ? (int64_t)kBlock : g.N;
         const CgAdjAcc<R> &a = acc[0];
         // Own state.
-        const R dr = state[so], r1 = state[kBlock + so];
-        const R jx = state[2 * kBlock + so], jy = state[3 * kBlock + so], jz = state[4 * kBlock + so];
+        const R dr = st[0], r1 = st[1];
+        const R jx = st[2], jy = st[3], jz = st[4];
         R s[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) s[k] = state[(5 + k) * kBlock + so];
+        for (int k = 0; k < 6; ++k) s[k] = st[5 + k];
         const R rho = R(1) + dr, r2 = rho - r1;
         const R inv_rho = R(1) / rho;
         // Colour gradient from the phase field of planes d-1, d, d+1.
@@ -365,8 +375,12 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(
         }
     };
 
+    R phv[4], stf[11];
     auto plane_step = [&](int p, R *own, R *ring) {
-        write_phi(p + 1);
+        const int dpl = p - 1;
+        const bool fin = dpl >= z0 && active;
+        if (fin) load_own(dpl, stf);
+        store_phi(p + 1, phv);
         publish(std::integral_constant<int, -1>(), own, h0);
         if (has_ring) {
             switch (ring_side) {
@@ -378,11 +392,11 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(
         }
         __syncthreads();
         if (p + 2 <= z_end) fetch(p + 2, own, ring);
+        if (p + 1 <= z_end) load_phi(p + 2, phv);
         gather_layer(std::integral_constant<int, -1>());
         gather_layer(std::integral_constant<int, 0>());
         gather_layer(std::integral_constant<int, 1>());
-        const int dpl = p - 1;
-        if (dpl >= z0 && active) finish(dpl);
+        if (fin) finish(dpl, stf);
         __syncthreads();
         acc[0] = acc[1];
         acc[1] = acc[2];
@@ -391,8 +405,11 @@ __global__ __launch_bounds__(TX *TY) void k_cg_adjoint_tile(
 
     // Phase field of planes z0-2 .. z0-1 before the loop; plane p+1 is added
     // in each step, so planes d-1 .. d+1 are present when plane d finishes.
-    write_phi(z0 - 2);
-    write_phi(z0 - 1);
+    load_phi(z0 - 2, phv);
+    store_phi(z0 - 2, phv);
+    load_phi(z0 - 1, phv);
+    store_phi(z0 - 1, phv);
+    load_phi(z0, phv);
     fetch(z0 - 1, la, rla);
     fetch(z0, lb, rlb);
     for (int p = z0 - 1; p <= z_end; p += 2) {
