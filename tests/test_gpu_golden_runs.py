@@ -25,7 +25,9 @@ that agrees with the oracle to 1e-13 before contact differs from it by about
 oracle's own spread, and node values in the neck differ by O(1).  From there
 on the observables are held to the tolerances of the droplet-collision
 configuration instead (centroids within 0.05 lattice units, the drop-averaged
-density within 1e-4 relative, the kinetic energy within 1e-3 relative);
+density within 1e-4 relative, the kinetic energy within 1e-3 relative), or
+ten times the oracle's own spread where that is larger (the head-on case's
+kinetic energy at steps 1700 and 1900: spread 1.1e-3 and 9.7e-4 relative);
 phi at the centre and the sampled nodes are reported, not compared (an FP32
 run adds rounding at every step, and while a film thins the oracle's spread
 from one perturbation at step 0 underestimates what that rounding causes:
@@ -133,10 +135,12 @@ def test_long_droplet_run_matches_oracle_observables(case, storage):
         else:
             checks = {
                 "mean_rho1": (got["mean_rho1"], ref["mean_rho1"],
-                              max(AFTER["mean_rho1_rel"] * abs(ref["mean_rho1"]), flips)),
-                "centroids": (got["centroids"], ref["centroids"], AFTER["centroids"]),
+                              np.maximum(max(AFTER["mean_rho1_rel"] * abs(ref["mean_rho1"]), flips),
+                                         10 * sp["mean_rho1"])),
+                "centroids": (got["centroids"], ref["centroids"], np.maximum(AFTER["centroids"], 10 * sp["centroids"])),
                 "kinetic_energy": (got["kinetic_energy"], ref["kinetic_energy"],
-                                   AFTER["kinetic_energy_rel"] * abs(ref["kinetic_energy"])),
+                                   np.maximum(AFTER["kinetic_energy_rel"] * abs(ref["kinetic_energy"]),
+                                              10 * sp["kinetic_energy"])),
             }
             _say(f"    t={t:5d} reported: phi at the centre {got['phi_centre']:+.4f} (oracle {ref['phi_centre']:+.4f})")
         for k, (a, b, bound) in checks.items():
