@@ -401,9 +401,12 @@ __global__ __launch_bounds__((kCgThreads<TX, TY, SR>), WPE) void k_cg_tile(const
         // so that each node emits exactly its species-1 mass (the identity
         // sum_i f1_i = rho1 holds in exact arithmetic: the weights sum to one
         // and the recolouring terms cancel in +-c pairs).
+        // One velocity layer at a time with cz a compile-time constant, so
+        // that every index below is static (a loop over cz is not always
+        // unrolled for D3Q27, and its arrays then go to scratch memory).
         R f1_moving = R(0);
-#pragma unroll
-        for (int cz = -1; cz <= 1; ++cz)
+        auto layer = [&](auto czc) {
+            constexpr int cz = decltype(czc)::value;
 #pragma unroll
             for (int sl = 0; sl < 9; ++sl) {
                 const int cx = sl % 3 - 1, cy = sl / 3 - 1;
@@ -420,6 +423,10 @@ __global__ __launch_bounds__((kCgThreads<TX, TY, SR>), WPE) void k_cg_tile(const
                     own_f[cz + 1] = f1;
                 }
             }
+        };
+        layer(std::integral_constant<int, -1>());
+        layer(std::integral_constant<int, 0>());
+        layer(std::integral_constant<int, 1>());
         own_h[1] = L[1].v[4];
         own_f[1] = v.v[1] - f1_moving;
     };
@@ -437,8 +444,8 @@ __global__ __launch_bounds__((kCgThreads<TX, TY, SR>), WPE) void k_cg_tile(const
         reconstruct_layer<Q, 1, R>(o.c, L[2]);
         const NSums ns = nsums(o);
         const F1Coef k = f1coef(o);
-#pragma unroll
-        for (int cz = -1; cz <= 1; ++cz)
+        auto layer = [&](auto czc) {  // cz static, as in publish()
+            constexpr int cz = decltype(czc)::value;
 #pragma unroll
             for (int t = -1; t <= 1; ++t) {
                 const int cx = ROW ? t : D, cy = ROW ? D : t;
@@ -454,6 +461,10 @@ __global__ __launch_bounds__((kCgThreads<TX, TY, SR>), WPE) void k_cg_tile(const
                     continue;
                 lds_hf[lds_at(s, bar, bbr)] = HF{hv, f1};
             }
+        };
+        layer(std::integral_constant<int, -1>());
+        layer(std::integral_constant<int, 0>());
+        layer(std::integral_constant<int, 1>());
     };
     using Up = std::integral_constant<int, 1>;
     using Down = std::integral_constant<int, -1>;
@@ -642,10 +653,13 @@ hipError_t launch_cg_step(const lbm_ctx *c, const void *in, void *out, bool phi_
     if (c->species != 2) return hipErrorNotSupported;
     using S2 = CgShape<4, 2, false>;
     using S8 = CgShape<8, 2, false>;
+#ifndef LBM_CG_Q27P
+#define LBM_CG_Q27P 8, 2, false
+#endif
     if (c->storage == LBM_STORE_F32)
         return c->q == 19 ? run<19, float, 64, CgShape<LBM_CG_P>, CgShape<LBM_CG_F>, CgShape<LBM_CG_C>>(
                                 c, in, out, phi_cached, normal)
-                          : run<27, float, 32, S8, S8, S8>(c, in, out, phi_cached, normal);
+                          : run<27, float, 32, CgShape<LBM_CG_Q27P>, S8, S8>(c, in, out, phi_cached, normal);
     if (c->storage == LBM_STORE_F64)
         return c->q == 19 ? run<19, double, 32, S2, S2, S2>(c, in, out, phi_cached, normal)
                           : run<27, double, 32, S2, S2, S2>(c, in, out, phi_cached, normal);
