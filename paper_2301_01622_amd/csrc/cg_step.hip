@@ -140,9 +140,9 @@ template <int TX, int TY, bool SR>
 constexpr int kCgThreads = SR ? TX * TY + (2 * TX + 63) / 64 * 64 + (2 * (TY + 2) + 63) / 64 * 64 : TX * TY;
 
 template <int Q, class R, int TX, int TY, bool FORCE, int WPE, bool COLL = false, bool SR = false>
-__global__ __launch_bounds__((kCgThreads<TX, TY, SR>), WPE) void k_cg_tile(const R *__restrict__ in, R *__restrict__ out, TileGrid g,
-                                                    R omega, R A9, R beta, const R *__restrict__ frc,
-                                                    R *__restrict__ phi_out)
+__global__ __launch_bounds__((kCgThreads<TX, TY, SR>), WPE) void k_cg_tile(
+    const R *__restrict__ in, R *__restrict__ out, TileGrid g, R omega, R A9, R beta, const R *__restrict__ frc,
+    R *__restrict__ phi_out)
 {
     static_assert(!(FORCE && COLL), "the split schedule applies the force in its collision pass");
     constexpr bool VEC3 = FORCE || COLL;  // three extra arrays per node (F, or n)
