@@ -308,6 +308,11 @@ def two_component(steps: int, warmup: int, repeats: int):
             ns.close()
             nc[scheme] = {"value": _rate(N, t["ms"]), "unit": "MLUPS", "ms_per_step": round(t["ms"], 5)}
         nc["speedup_vs_population_lb"] = round(nc["population"]["ms_per_step"] / nc["moment"]["ms_per_step"], 3)
+        # The same collision on the D3Q27 lattice.
+        q27 = LBM((512, 256, 256), 27, 0.8, species=2, storage="f32", sigma=0.01, beta=0.7, stream=stream)
+        q27.set_equilibrium(prim, uu)
+        t27 = time_steps(q27, stream, steps, warmup, repeats)["ms"]
+        q27.close()
     return {
         "workload": "512x256x256 two-component droplet collision, D3Q19, FP32 (rho-1, rho1, j, P), tau=0.8, "
                     "sigma=0.01, beta=0.7, R=40, u=+-0.05",
@@ -337,6 +342,7 @@ def two_component(steps: int, warmup: int, repeats: int):
             "fused_speedup": round(stm / ms, 3),
         },
         "near_contact": {"A_h": 0.01, "h_max": 4, **nc},
+        "d3q27": {"value": _rate(N, t27), "unit": "MLUPS", "ms_per_step": round(t27, 5)},
         "adjoint": adjoint,
     }
 
