@@ -60,7 +60,7 @@ def gpu_warmup(sim, min_ms: float) -> float:
     import torch
     t0 = time.perf_counter()
     while (time.perf_counter() - t0) * 1e3 < min_ms:
-        sim.step(2)
+        sim.step(20)  # several launches per synchronisation, so the GPU stays busy
         torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1e3
 
@@ -398,7 +398,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--repeats", type=int, default=3,
+    ap.add_argument("--repeats", type=int, default=5,
                     help="timed regions of --steps steps each; the median is reported")
     ap.add_argument("--gpu-warmup-ms", type=float, default=300.0,
                     help="wall-clock GPU warm-up before the first timed region")
