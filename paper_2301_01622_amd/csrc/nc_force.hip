@@ -28,6 +28,7 @@
 // per block.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -68,39 +69,44 @@ constexpr int kHmaxMax = 32;
 
 // Sign summary of the phase field: for the block (bx, by) of 64 x 4 nodes
 // of plane z, bit k (k = 0..3) is set if a node of x-group k (16 nodes) has
-// phi > 0, bit 4 + k if one has phi < 0.  One wave per row; each workgroup
-// covers kZB planes.
-template <class R>
-__global__ __launch_bounds__(kNX *kNY) void k_phi_signs(const R *__restrict__ phi, int nx, int ny, int nz,
-                                                        uint8_t *__restrict__ sig)
+// phi > 0, bit 4 + k if one has phi < 0.  A wave covers one block column of
+// 64 x-nodes, each lane one x over the block's 4 rows (the signs of the rows
+// are OR-ed in the lane, then one ballot per plane); the waves of a
+// workgroup (blockDim.x / 64, at most 4) cover consecutive block columns, so
+// that each row is read in pieces of up to 1 KiB, and ZB planes.
+constexpr int kSignWavesMax = 4;
+template <class R, int ZB>
+__global__ __launch_bounds__(64 * kSignWavesMax) void k_phi_signs(const R *__restrict__ phi, int nx, int ny, int nz,
+                                                                 uint8_t *__restrict__ sig)
 {
-    const int x = blockIdx.x * kNX + threadIdx.x, y = blockIdx.y * kNY + threadIdx.y;
-    const int z0 = blockIdx.z * kZB, zn = min(kZB, nz - z0);
-    __shared__ unsigned int bits[kZB];
-    if (threadIdx.y == 0 && threadIdx.x < kZB) bits[threadIdx.x] = 0u;
-    R f[kZB];
-    const bool in = x < nx && y < ny;
+    const int lane = threadIdx.x % 64;
+    const int bx = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64, by = blockIdx.y;
+    const int gx = (nx + kNX - 1) / kNX, gy = (ny + kNY - 1) / kNY;
+    const int x = bx * kNX + lane, y0 = by * kNY;
+    const int z0 = blockIdx.z * ZB, zn = min(ZB, nz - z0);
+    const bool in = x < nx;
 #pragma unroll
-    for (int k = 0; k < kZB; ++k)
-        f[k] = in && k < zn ? phi[(int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * (z0 + k))] : R(0);
-    __syncthreads();
+    for (int k = 0; k < ZB; ++k) {
+        bool pos = false, neg = false;
 #pragma unroll
-    for (int k = 0; k < kZB; ++k) {
-        const unsigned long long pos = __ballot(f[k] > R(0)), neg = __ballot(f[k] < R(0));
-        if (threadIdx.x == 0) {
+        for (int r = 0; r < kNY; ++r) {
+            const R f = in && y0 + r < ny && k < zn
+                            ? phi[(int64_t)x + (int64_t)nx * ((int64_t)(y0 + r) + (int64_t)ny * (z0 + k))]
+                            : R(0);
+            pos = pos || f > R(0);
+            neg = neg || f < R(0);
+        }
+        const unsigned long long bp = __ballot(pos), bn = __ballot(neg);
+        if (lane == 0 && bx < gx && k < zn) {
             unsigned int b = 0u;
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                if ((pos >> (16 * g)) & 0xffffull) b |= 1u << g;
-                if ((neg >> (16 * g)) & 0xffffull) b |= 1u << (4 + g);
+                if ((bp >> (16 * g)) & 0xffffull) b |= 1u << g;
+                if ((bn >> (16 * g)) & 0xffffull) b |= 1u << (4 + g);
             }
-            if (b) atomicOr(&bits[k], b);
+            sig[bx + (int64_t)gx * (by + (int64_t)gy * (z0 + k))] = (uint8_t)b;
         }
     }
-    __syncthreads();
-    if (threadIdx.y == 0 && (int)threadIdx.x < zn)
-        sig[blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * (z0 + threadIdx.x))] =
-            (uint8_t)bits[threadIdx.x];
 }
 
 // Group indices (groups of width g over [0, n)) met by the coordinates
@@ -298,9 +304,17 @@ hipError_t run(const lbm_ctx *c, const void *moments, const R *phi_in, R *phi_bu
     }
     uint8_t *sig = nc_block_flags(c), *dirty = sig + nc_blocks(c);
     const dim3 zgrid(grid.x, grid.y, (c->nz + kZB - 1) / kZB);
-    hipLaunchKernelGGL((k_phi_signs<R>), zgrid, block, 0, c->stream, phi, c->nx, c->ny, c->nz, sig);
     if (c->nc_hmax > kHmaxMax) return hipErrorInvalidValue;
     const bool few = (int64_t)zgrid.x * zgrid.y * zgrid.z < 16 * 256;
+    // The sign pass: up to 4 block columns per workgroup; on small grids two
+    // planes per workgroup instead of kZB, so that the grid still fills the
+    // chip.
+    const unsigned sw = std::min<unsigned>(kSignWavesMax, grid.x);
+    const dim3 sgrid((grid.x + sw - 1) / sw, grid.y, few ? (c->nz + 1) / 2 : zgrid.z);
+    if (few)
+        hipLaunchKernelGGL((k_phi_signs<R, 2>), sgrid, dim3(64 * sw), 0, c->stream, phi, c->nx, c->ny, c->nz, sig);
+    else
+        hipLaunchKernelGGL((k_phi_signs<R, kZB>), sgrid, dim3(64 * sw), 0, c->stream, phi, c->nx, c->ny, c->nz, sig);
     const dim3 block3(kNX, kNY, few ? 2 : 1);
     auto force = [&](auto q, auto nzc) {
         hipLaunchKernelGGL((k_nc_force<decltype(q)::value, R, decltype(nzc)::value>), zgrid, block3, 0, c->stream,
