@@ -128,6 +128,8 @@ struct SlotLayout {
 // equilibrium, (1 - omega/2)(u* F + F u*) added to the collided S, j + F
 // streamed; the phase field phi = 2 rho1/rho - 1 of the stored output is
 // written to phi_out (N values, x fastest) for the next step's force.
+// fdirty holds the near-contact pass's per-block flags: where a node's block
+// flag is zero its force is zero and is not read.
 // COLL (split schedule): `in` holds post-collision moments (S' with the
 // perturbation, j + F under a force) and frc the interface normal n (three
 // arrays of N values); the step then only reconstructs, recolours, pulls and
@@ -142,7 +144,7 @@ constexpr int kCgThreads = SR ? TX * TY + (2 * TX + 63) / 64 * 64 + (2 * (TY + 2
 template <int Q, class R, int TX, int TY, bool FORCE, int WPE, bool COLL = false, bool SR = false>
 __global__ __launch_bounds__((kCgThreads<TX, TY, SR>), WPE) void k_cg_tile(
     const R *__restrict__ in, R *__restrict__ out, TileGrid g, R omega, R A9, R beta, const R *__restrict__ frc,
-    R *__restrict__ phi_out)
+    R *__restrict__ phi_out, const uint8_t *__restrict__ fdirty)
 {
     static_assert(!(FORCE && COLL), "the split schedule applies the force in its collision pass");
     constexpr bool VEC3 = FORCE || COLL;  // three extra arrays per node (F, or n)
@@ -228,6 +230,15 @@ __global__ __launch_bounds__((kCgThreads<TX, TY, SR>), WPE) void k_cg_tile(
     };
     const int64_t own_lin = VEC3 ? lin_src(h0) : 0;
     const int64_t ring_lin = VEC3 && has_ring ? lin_src(hr) : 0;
+    // Force-flag blocks of the two source nodes (FORCE), in plane 0.
+    const int fgx = (g.nx + kNcBlockX - 1) / kNcBlockX;
+    const int64_t fgxy = (int64_t)fgx * ((g.ny + kNcBlockY - 1) / kNcBlockY);
+    auto blk_src = [&](int h) -> int64_t {
+        return wrap_coord(x0 - 1 + h % SX, g.nx) / kNcBlockX +
+               (int64_t)fgx * (wrap_coord(y0 - 1 + h / SX, g.ny) / kNcBlockY);
+    };
+    const int64_t own_blk = FORCE ? blk_src(h0) : 0;
+    const int64_t ring_blk = FORCE && has_ring ? blk_src(hr) : 0;
     const int64_t plane_lin = (int64_t)g.nx * g.ny;
     const int64_t outer_xy =
         has_outer ? g.lay.xy(wrap_coord(x0 - 2 + ko % FX, g.nx), wrap_coord(y0 - 2 + ko / FX, g.ny))
@@ -261,7 +272,21 @@ __global__ __launch_bounds__((kCgThreads<TX, TY, SR>), WPE) void k_cg_tile(
     // With SR a ring thread keeps its node in the `own` registers.
     const uint32_t node_vo = SR && !interior ? ring_vo : own_vo;
     const uint32_t node_lvo = SR && !interior ? ring_lvo : own_lvo;
+    const int64_t node_blk = SR && !interior ? ring_blk : own_blk;
+    // FORCE: the force flags of the two source nodes for the next plane
+    // fetched, loaded one fetch ahead (before that fetch's moments, so that
+    // waiting for them never waits for the moments in flight).
+    uint8_t nfo = 1, nfr = 1;
+    auto load_flags = [&](int p) {
+        if (!FORCE) return;
+        const int64_t zb = (int64_t)zwrap(p) * fgxy;
+        if (!SR || interior || has_ring) nfo = fdirty[zb + node_blk];
+        if (!SR && has_ring) nfr = fdirty[zb + ring_blk];
+    };
+    // Planes are fetched in increasing order up to z_end + 1.
     auto fetch = [&](int p, PlaneRegs &r) {
+        const bool fo = !FORCE || nfo != 0, fr = !FORCE || nfr != 0;
+        if (p + 1 <= z_end + 1) load_flags(p + 1);
         const __amdgpu_buffer_rsrc_t rs = plane_buf(in + (int64_t)zwrap(p) * plane, plane);
         if (!SR || interior || has_ring) {
 #pragma unroll
@@ -281,14 +306,22 @@ __global__ __launch_bounds__((kCgThreads<TX, TY, SR>), WPE) void k_cg_tile(
             const __amdgpu_buffer_rsrc_t fy = plane_buf(frc + g.N + zl, plane_lin);
             const __amdgpu_buffer_rsrc_t fz = plane_buf(frc + 2 * g.N + zl, plane_lin);
             if (!SR || interior || has_ring) {
-                r.fox = buf_load<R>(fx, node_lvo, 0);
-                r.foy = buf_load<R>(fy, node_lvo, 0);
-                r.foz = buf_load<R>(fz, node_lvo, 0);
+                if (fo) {
+                    r.fox = buf_load<R>(fx, node_lvo, 0);
+                    r.foy = buf_load<R>(fy, node_lvo, 0);
+                    r.foz = buf_load<R>(fz, node_lvo, 0);
+                } else {
+                    r.fox = r.foy = r.foz = R(0);
+                }
             }
             if (!SR && has_ring) {
-                r.frx = buf_load<R>(fx, ring_lvo, 0);
-                r.fry = buf_load<R>(fy, ring_lvo, 0);
-                r.frz = buf_load<R>(fz, ring_lvo, 0);
+                if (fr) {
+                    r.frx = buf_load<R>(fx, ring_lvo, 0);
+                    r.fry = buf_load<R>(fy, ring_lvo, 0);
+                    r.frz = buf_load<R>(fz, ring_lvo, 0);
+                } else {
+                    r.frx = r.fry = r.frz = R(0);
+                }
             }
         }
     };
@@ -538,6 +571,7 @@ __global__ __launch_bounds__((kCgThreads<TX, TY, SR>), WPE) void k_cg_tile(
     };
 
     // Prologue: phase field of planes z0-2 and z0-1, moments of z0-1 and z0.
+    load_flags(z0 - 2);
     fetch(z0 - 2, pa);
     write_phi(z0 - 2, pa);
     fetch(z0 - 1, pa);
@@ -581,7 +615,8 @@ struct CgShape {
 };
 
 template <int Q, class R, int TX, class SH, bool FORCE, bool COLL>
-hipError_t launch_tile(const lbm_ctx *c, const void *in, void *out, const R *frc, R *phi_out)
+hipError_t launch_tile(const lbm_ctx *c, const void *in, void *out, const R *frc, R *phi_out,
+                       const uint8_t *fdirty = nullptr)
 {
     constexpr int TY = SH::TY, NTH = kCgThreads<TX, TY, SH::SR>;
     // Waves per SIMD the register allocation must leave room for.
@@ -600,7 +635,7 @@ hipError_t launch_tile(const lbm_ctx *c, const void *in, void *out, const R *frc
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((k_cg_tile<Q, R, TX, TY, FORCE, WPE, COLL, SH::SR>), dim3((unsigned)blocks), dim3(NTH), 0,
                        c->stream, static_cast<const R *>(in), static_cast<R *>(out), g, (R)c->omega,
-                       (R)(c->A / 9.0), (R)c->beta, frc, phi_out);
+                       (R)(c->A / 9.0), (R)c->beta, frc, phi_out, fdirty);
     return hipGetLastError();
 }
 
@@ -617,7 +652,8 @@ hipError_t run(const lbm_ctx *c, const void *in, void *out, bool phi_cached, con
         R *phi = static_cast<R *>(c->scratch_nc) + 3 * c->N;
         hipError_t e = phi_cached ? launch_nc_force(c, nullptr, phi) : launch_nc_force(c, in, nullptr);
         if (e != hipSuccess) return e;
-        return launch_tile<Q, R, TX, F, true, false>(c, in, out, static_cast<const R *>(c->scratch_nc), phi);
+        return launch_tile<Q, R, TX, F, true, false>(c, in, out, static_cast<const R *>(c->scratch_nc), phi,
+                                                     nc_block_flags(c) + nc_blocks(c));
     }
     return launch_tile<Q, R, TX, P, false, false>(c, in, out, nullptr, nullptr);
 }

@@ -103,7 +103,12 @@ hipError_t launch_costate_convert(const lbm_ctx *c, const void *src, void *dst, 
 // arrays of N), from the phase field `phi` (N values, population scheme) or,
 // if phi is NULL, from the moment state `moments`.  The scratch must start
 // zeroed (nc_scratch_bytes bytes): per-block flags record where the force
-// arrays may hold non-zero values.
+// arrays may hold non-zero values.  A block is kNcBlockX x kNcBlockY nodes of
+// one plane, block (bx, by) of plane z has index bx + gx (by + gy z) (gx, gy:
+// blocks per row and column), and nc_blocks(c) of them follow the sign
+// summary at nc_block_flags(c): after each force pass, a block whose flag is
+// zero holds zeros in all three force arrays.
+constexpr int kNcBlockX = 64, kNcBlockY = 4;
 hipError_t launch_nc_force(const lbm_ctx *c, const void *moments, const void *phi);
 int64_t nc_blocks(const lbm_ctx *c);
 size_t nc_scratch_bytes(const lbm_ctx *c);

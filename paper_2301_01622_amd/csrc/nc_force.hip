@@ -42,7 +42,7 @@ namespace {
 
 // Launch shape of the per-node kernels: 64 x 4 threads over x and y, one z
 // plane per block row (no index division).
-constexpr int kNX = 64, kNY = 4;
+constexpr int kNX = kNcBlockX, kNY = kNcBlockY;
 
 // Phase field phi = (rho1 - rho2)/rho = 2 rho1/rho - 1 of the moment state
 // (stored fields dr = rho - 1 and rho1), public layout.
