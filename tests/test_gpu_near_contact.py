@@ -36,8 +36,10 @@ def _contact_state(oracle, shape, gap=3.0, R=5.0):
 
 @pytest.mark.parametrize("q", [19, 27])
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
-def test_near_contact_moment_scheme_matches_oracle(LBM, oracle, q, storage, tol):
-    shape = (14, 17, 31)
+@pytest.mark.parametrize("shape", [(14, 17, 31), (14, 17, 132)])
+def test_near_contact_moment_scheme_matches_oracle(LBM, oracle, q, storage, tol, shape):
+    # nx = 132: three 64-wide block columns of the force pass, the last one
+    # 4 nodes wide, and the film across the first column boundary.
     _say(f"near-contact moment scheme {shape} D3Q{q} {storage} 6 steps")
     H, r1 = _contact_state(oracle, shape)
     F, h = oracle.nc_force(2 * r1 - 1, q, AH, HMAX)
